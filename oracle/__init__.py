@@ -1,0 +1,174 @@
+"""FP64 CPU oracle for the 25-point leapfrog wave propagator (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY.  The test-suite, the smoke check and the
+CPU-baseline leg of the benchmark use this package; the product path never
+imports it.  It shares no code with the HIP library: ``oracle.c`` restates the
+paper's method (Section III: Eq. 1, Eq. 2, the 25-point Laplacian and
+Algorithm 1; Section IV-B ghost cells; Section IV-C centre folding; Section
+IV-D source injection) as plain loops in double precision.
+
+All arrays are dense interior arrays ``[nz][ny][nx]`` (x fastest) unless a
+function says it takes a padded array ``[nz+8][ny+8][nx+8]``.
+
+Parity status per function (what pins it lives in ``tests/test_oracle_*``):
+  coefficients     pinned (exact rationals, moment conditions, degree-10 residual)
+  laplacian        pinned (polynomial exactness, degree-10 error, convergence,
+                   Kronecker-sum brute force)
+  run              pinned (impulse response, plane-wave dispersion, energy,
+                   reciprocity, brute force, restart equivalence)
+  sponge_profile   parity unpinned beyond W = 0 reduction and its own
+                   definition (the sponge is a chosen published method, not
+                   something the paper fixes)
+  step_points      pinned against ``run`` (same update, pointwise)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SOURCE = os.path.join(_HERE, "oracle.c")
+
+BC_ZERO = 0
+BC_PERIODIC = 1
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc (FP64, no fast-math,
+    no FMA contraction)."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SOURCE):
+        cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-o", LIB_PATH + ".tmp", SOURCE, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        build()
+    lib = ctypes.CDLL(LIB_PATH)
+    dp = ctypes.POINTER(ctypes.c_double)
+    fp = ctypes.POINTER(ctypes.c_float)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    ci, cd = ctypes.c_int, ctypes.c_double
+    lib.oracle_coefficients.argtypes = [dp]
+    lib.oracle_coefficients.restype = None
+    lib.oracle_sponge_profile.argtypes = [ci, ci, cd, dp]
+    lib.oracle_sponge_profile.restype = None
+    lib.oracle_laplacian.argtypes = [ci, ci, ci, cd, cd, cd, dp, dp, ci]
+    lib.oracle_laplacian.restype = ci
+    lib.oracle_run.argtypes = [ci, ci, ci, cd, cd, cd, ci, ci, cd, dp, ci, dp, ci, ci, ci,
+                               ci, ip, dp, dp, dp, ci]
+    lib.oracle_run.restype = ci
+    lib.oracle_step_points.argtypes = [ci, ci, ci, cd, cd, cd, ci, cd, fp, fp, fp, ci, ci,
+                                       ci, ci, cd, ci, ip, dp]
+    lib.oracle_step_points.restype = ci
+    _lib = lib
+    return lib
+
+
+def default_threads() -> int:
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:  # pragma: no cover
+        return max(1, os.cpu_count() or 1)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def coefficients() -> np.ndarray:
+    """c_0..c_4 of the 8th-order second derivative (closed form, FP64)."""
+    c = np.zeros(5, dtype=np.float64)
+    _load().oracle_coefficients(_dptr(c))
+    return c
+
+
+def sponge_profile(n: int, width: int, alpha: float) -> np.ndarray:
+    g = np.zeros(n, dtype=np.float64)
+    _load().oracle_sponge_profile(int(n), int(width), float(alpha), _dptr(g))
+    return g
+
+
+def laplacian(a_pad: np.ndarray, h, nthreads: int | None = None) -> np.ndarray:
+    """25-point Laplacian of a padded array [nz+8][ny+8][nx+8] (ghost values as
+    given); returns the interior [nz][ny][nx].  ``h`` = (dx, dy, dz)."""
+    a_pad = np.ascontiguousarray(a_pad, dtype=np.float64)
+    nz, ny, nx = (d - 8 for d in a_pad.shape)
+    out = np.zeros((nz, ny, nx), dtype=np.float64)
+    dx, dy, dz = h
+    rc = _load().oracle_laplacian(nx, ny, nz, dx, dy, dz, _dptr(a_pad), _dptr(out),
+                                  nthreads or default_threads())
+    if rc != 0:
+        raise ValueError(f"oracle_laplacian rejected its arguments (rc={rc})")
+    return out
+
+
+def run(k: np.ndarray, h, nt: int, *, s=None, src=(0, 0, 0), rec=None, a_cur=None,
+        a_prev=None, sponge_width: int = 0, sponge_alpha: float = 0.0, bc: int = BC_ZERO,
+        nthreads: int | None = None):
+    """Run ``nt`` steps.  Returns (a_cur, a_prev, traces): u^{n0+nt},
+    u^{n0+nt-1} and traces [nt][nrec] (row j = field after step j)."""
+    k = np.ascontiguousarray(k, dtype=np.float64)
+    nz, ny, nx = k.shape
+    dx, dy, dz = h
+    a_cur = np.zeros_like(k) if a_cur is None else np.array(a_cur, dtype=np.float64, copy=True)
+    a_prev = np.zeros_like(k) if a_prev is None else np.array(a_prev, dtype=np.float64, copy=True)
+    assert a_cur.shape == k.shape and a_prev.shape == k.shape
+    rec = np.zeros((0, 3), dtype=np.int32) if rec is None else np.ascontiguousarray(rec, dtype=np.int32).reshape(-1, 3)
+    nrec = rec.shape[0]
+    traces = np.zeros((max(nt, 0), nrec), dtype=np.float64)
+    if s is not None:
+        s = np.ascontiguousarray(s, dtype=np.float64)
+        assert s.shape[0] >= nt
+        sp = _dptr(s)
+    else:
+        sp = None
+    rc = _load().oracle_run(nx, ny, nz, dx, dy, dz, int(bc), int(sponge_width), float(sponge_alpha),
+                            _dptr(k), int(nt), sp, int(src[0]), int(src[1]), int(src[2]), nrec,
+                            _iptr(rec), _dptr(a_cur), _dptr(a_prev), _dptr(traces),
+                            nthreads or default_threads())
+    if rc != 0:
+        raise ValueError(f"oracle_run rejected its arguments (rc={rc})")
+    return a_cur, a_prev, traces
+
+
+def step_points(k32, u_cur32, u_prev32, h, pts, *, sponge_width=0, sponge_alpha=0.0,
+                src=None, src_value=0.0) -> np.ndarray:
+    """One update at the listed points [npts][3] (z, y, x), in FP64 from FP32
+    copies of k, u^n and u^{n-1}."""
+    k32 = np.ascontiguousarray(k32, dtype=np.float32)
+    u_cur32 = np.ascontiguousarray(u_cur32, dtype=np.float32)
+    u_prev32 = np.ascontiguousarray(u_prev32, dtype=np.float32)
+    nz, ny, nx = k32.shape
+    pts = np.ascontiguousarray(pts, dtype=np.int32).reshape(-1, 3)
+    out = np.zeros(pts.shape[0], dtype=np.float64)
+    dx, dy, dz = h
+    has_src = src is not None
+    sz, sy, sx = src if has_src else (0, 0, 0)
+    rc = _load().oracle_step_points(nx, ny, nz, dx, dy, dz, int(sponge_width), float(sponge_alpha),
+                                    _fptr(k32), _fptr(u_cur32), _fptr(u_prev32), int(has_src),
+                                    int(sz), int(sy), int(sx), float(src_value), pts.shape[0],
+                                    _iptr(pts), _dptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_step_points rejected its arguments (rc={rc})")
+    return out

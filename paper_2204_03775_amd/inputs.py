@@ -1,0 +1,177 @@
+"""Seeded synthetic inputs for the wave propagator.
+
+This module only *generates inputs*: velocity models, source wavelets,
+source/receiver positions and time steps.  It holds none of the propagator's
+arithmetic and imports neither the HIP library nor the oracle, so both sides
+of every parity check read exactly the same inputs from here.
+
+The paper runs on synthetic grids whose velocity model it does not state
+(Section V-B, Tables 2 and 3); the workloads here are synthetic too:
+
+* ``small_parity``: 64^3, constant 1500 m/s, h = 10 m, dt = 1 ms, 100 steps,
+  15 Hz Ricker at the centre, 16 seeded random receivers, zero ghost layer,
+  no sponge.
+* ``large_shot``: 512^3, h = 10 m, dt = 0.8 of the stability limit at
+  4500 m/s, 1000 steps, five equal layers 1500..4500 m/s times
+  (1 + 0.05 p) with p Gaussian-smoothed white noise scaled to max |p| = 1,
+  20-cell sponge, 12 Hz Ricker near the top, 256 receivers on a line.
+
+Random draws use ``numpy.random.default_rng(2204 + i)`` for workload i.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Maximum of the 8th-order second-derivative symbol |c_0 + 2 sum c_m cos(m pi)|
+# (reached at the Nyquist wavenumber), used only to pick a stable dt.
+SYMBOL_MAX = 2048.0 / 315.0
+
+
+def stable_courant_limit(ndim: int = 3) -> float:
+    """Largest v*dt/h for which leapfrog with this stencil stays stable on a
+    cubic grid: k * ndim * SYMBOL_MAX / h^2 <= 4."""
+    return 2.0 / math.sqrt(ndim * SYMBOL_MAX)
+
+
+def cfl_dt(vmax: float, h: float, fraction: float = 0.8) -> float:
+    return fraction * stable_courant_limit(3) * h / vmax
+
+
+def ricker(freq: float, nt: int, dt: float, t0: float | None = None) -> np.ndarray:
+    """Ricker wavelet w(t_n), t_n = n dt, peak at t0 (default 1/freq)."""
+    t0 = 1.0 / freq if t0 is None else t0
+    tau = np.arange(nt, dtype=np.float64) * dt - t0
+    a = (math.pi * freq * tau) ** 2
+    return (1.0 - 2.0 * a) * np.exp(-a)
+
+
+def point_source_values(w: np.ndarray, v_src: float, dt: float, h) -> np.ndarray:
+    """Values added to the source cell per step: dt^2 V^2 f with f a point
+    source of time function w spread over one cell (1/(dx dy dz))."""
+    dx, dy, dz = h
+    return (v_src * dt) ** 2 * np.asarray(w, dtype=np.float64) / (dx * dy * dz)
+
+
+def layered_velocity(nz: int, ny: int, nx: int, velocities, *, perturb: float = 0.0,
+                     sigma: float = 4.0, seed: int = 0) -> np.ndarray:
+    """Equal-thickness layers along z (top to bottom) times (1 + perturb * p),
+    p = white noise smoothed by a separable Gaussian and scaled to max|p| = 1.
+    Returned as float32 [nz][ny][nx] (large grids); values are exact to
+    float32 rounding of the FP64 construction per layer."""
+    vel = np.asarray(velocities, dtype=np.float64)
+    nl = len(vel)
+    layer = np.minimum((np.arange(nz) * nl) // nz, nl - 1)
+    vz = vel[layer].astype(np.float32)
+    v = np.empty((nz, ny, nx), dtype=np.float32)
+    v[...] = vz[:, None, None]
+    if perturb:
+        p = smoothed_noise((nz, ny, nx), sigma, seed)
+        v *= (1.0 + perturb * p).astype(np.float32)
+    return v
+
+
+def smoothed_noise(shape, sigma: float, seed: int) -> np.ndarray:
+    from scipy.ndimage import gaussian_filter1d
+
+    rng = np.random.default_rng(seed)
+    p = rng.standard_normal(shape, dtype=np.float32)
+    for ax in range(3):
+        p = gaussian_filter1d(p, sigma, axis=ax, mode="nearest", truncate=4.0)
+    p /= np.float32(np.max(np.abs(p)))
+    return p
+
+
+def random_receivers(shape, n: int, seed: int) -> np.ndarray:
+    """n distinct interior points drawn without replacement; [n][3] (z, y, x)."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    flat = rng.choice(nz * ny * nx, size=n, replace=False)
+    z, y, x = np.unravel_index(flat, (nz, ny, nx))
+    return np.stack([z, y, x], axis=1).astype(np.int32)
+
+
+def line_receivers(z: int, y: int, x0: int, x1: int, n: int) -> np.ndarray:
+    xs = [x0 + int(round(r * (x1 - x0) / (n - 1))) for r in range(n)]
+    return np.array([[z, y, x] for x in xs], dtype=np.int32)
+
+
+@dataclass
+class Problem:
+    """One forward run: grid, physics, source, receivers and model."""
+
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    h: tuple
+    dt: float
+    nt: int
+    sponge_width: int
+    sponge_alpha: float
+    src: tuple
+    rec: np.ndarray
+    s: np.ndarray            # [nt] FP64 value added to the source cell per step
+    v: np.ndarray = field(repr=False)   # [nz][ny][nx] velocity (float32 or float64)
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def points(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def k64(self) -> np.ndarray:
+        """V^2 dt^2 per cell, FP64."""
+        v = self.v.astype(np.float64)
+        return (v * self.dt) ** 2
+
+    def k32(self) -> np.ndarray:
+        """V^2 dt^2 per cell rounded once to FP32."""
+        return self.k64().astype(np.float32)
+
+
+def small_parity() -> Problem:
+    n = 64
+    h = (10.0, 10.0, 10.0)
+    dt, nt = 1e-3, 100
+    v = np.full((n, n, n), 1500.0, dtype=np.float64)
+    src = (n // 2, n // 2, n // 2)
+    w = ricker(15.0, nt, dt)
+    return Problem("small_parity", n, n, n, h, dt, nt, 0, 0.0, src,
+                   random_receivers((n, n, n), 16, 2204),
+                   point_source_values(w, 1500.0, dt, h), v)
+
+
+def large_shot(n: int = 512, nt: int = 1000) -> Problem:
+    h = (10.0, 10.0, 10.0)
+    dt = cfl_dt(4500.0, 10.0, 0.8)
+    v = layered_velocity(n, n, n, [1500.0, 2250.0, 3000.0, 3750.0, 4500.0],
+                         perturb=0.05, sigma=4.0, seed=2205)
+    src = (25, n // 2, n // 2)
+    w = ricker(12.0, nt, dt)
+    rec = line_receivers(22, n // 2, 20, n - 21, 256)
+    return Problem("large_shot", n, n, n, h, dt, nt, 20, 0.015, src, rec,
+                   point_source_values(w, float(v[src]), dt, h), v)
+
+
+def random_problem(nx: int, ny: int, nz: int, nt: int, *, seed: int, h=(10.0, 12.0, 8.0),
+                   sponge_width: int = 0, sponge_alpha: float = 0.015, nrec: int = 8,
+                   vmin: float = 1500.0, vmax: float = 3500.0, freq: float = 25.0,
+                   courant: float = 0.6) -> Problem:
+    """Small heterogeneous problem for edge-case parity: anisotropic spacing,
+    random smooth-free velocities, source and receivers anywhere inside."""
+    rng = np.random.default_rng(seed)
+    v = rng.uniform(vmin, vmax, size=(nz, ny, nx))
+    # stable for anisotropic spacing: k * SYMBOL_MAX * sum(1/h^2) <= 4
+    lim = 2.0 / math.sqrt(SYMBOL_MAX * sum(1.0 / hh ** 2 for hh in h))
+    dt = courant * lim / vmax
+    src = tuple(int(rng.integers(0, d)) for d in (nz, ny, nx))
+    npts = nx * ny * nz
+    rec = random_receivers((nz, ny, nx), min(nrec, npts), seed + 1)
+    w = ricker(freq, nt, dt, t0=1.2 / freq)
+    return Problem(f"random_{nx}x{ny}x{nz}", nx, ny, nz, tuple(h), dt, nt, sponge_width,
+                   sponge_alpha, src, rec, point_source_values(w, float(v[src]), dt, h), v)
