@@ -1,0 +1,158 @@
+/*
+ * wave.h -- C ABI of libwave.so, an MI355X (gfx950) propagator for the 3-D
+ * constant-density acoustic wave equation.
+ *
+ * What one step computes (paper, Section III: Eq. 1, Eq. 2 and the 25-point
+ * Laplacian; Algorithm 1 for the time loop; Section IV-C for counting the
+ * centre once; Section IV-D for the source), in single precision:
+ *
+ *   lap(u)   = sum_{a in x,y,z} (1/h_a^2) [ c0 u + sum_{m=1..4} c_m (u(+m e_a) + u(-m e_a)) ]
+ *              with the 8th-order weights c = (-205/72, 8/5, -1/5, 8/315, -1/560);
+ *   u^{n+1}  = G (2 u^n - G u^{n-1} + k lap(u^n)),  k = V^2 dt^2 per cell,
+ *              G = gx(x) gy(y) gz(z) a Cerjan sponge (G = 1 with no sponge,
+ *              where this is Eq. 2 exactly);
+ *   u^{n+1}[src] += s_n                (value supplied by the caller);
+ *   trace[n][r]   = u^{n+1}[rec_r]     (after the source is added).
+ *
+ * The paper gives no programming interface; this one is designed for a GPU
+ * that owns the fields.  Conventions for every call:
+ *   - return value: WAVE_OK (0) or a negative WAVE_E* code; nothing throws;
+ *     wave_strerror() names a code, wave_last_error() gives the message of
+ *     the last failure on a context;
+ *   - "device pointer" = memory allocated on the context's GPU by the caller
+ *     (hipMalloc, a torch tensor); the library never frees caller memory;
+ *   - host arrays are only read during the call;
+ *   - a context is not thread-safe; distinct contexts are independent;
+ *   - work is enqueued on the context's stream and returns before it runs;
+ *     wave_sync() waits for it and reports asynchronous GPU errors.
+ *
+ * Field layout (every wave field and k share it; see wave_layout):
+ *   planes [nz+8] x rows [ny+8] x pitch_x elements, x fastest.  A ghost layer
+ *   of 4 cells surrounds the interior on every face (paper Section IV-B
+ *   extends each column by 4 cells on both sides; here the same is done on
+ *   all three axes).  Interior point (z, y, x), 0 <= x < nx etc., is element
+ *       ((z + 4) * (ny + 8) + (y + 4)) * pitch_x + x_offset + x.
+ *   Ghost cells must be zero in u fields (zero Dirichlet boundary) and the
+ *   library never writes them.  x_offset makes every interior row start on a
+ *   128-byte boundary.
+ */
+#ifndef WAVE_H
+#define WAVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define WAVE_OK 0
+#define WAVE_EINVAL (-1)    /* bad argument; nothing was enqueued */
+#define WAVE_EUNSTABLE (-2) /* k too large for the leapfrog stability limit */
+#define WAVE_ESTATE (-3)    /* call not valid in the context's current state */
+#define WAVE_ENOMEM (-4)    /* host or device allocation failed */
+#define WAVE_EHIP (-5)      /* a HIP runtime call or a kernel failed */
+
+/* storage types */
+#define WAVE_F32 0
+
+typedef struct wave_layout_t {
+    int64_t pitch_x;  /* elements per row (multiple of 32) */
+    int64_t rows;     /* rows per plane = ny + 8 */
+    int64_t planes;   /* planes = nz + 8 */
+    int64_t x_offset; /* element offset of interior x = 0 within a row */
+    int64_t plane;    /* elements per plane = pitch_x * rows */
+    int64_t elems;    /* elements per field = plane * planes */
+    int64_t bytes;    /* bytes per field */
+} wave_layout_t;
+
+typedef struct wave_params_t {
+    int32_t nx, ny, nz;   /* interior size, each >= 1 */
+    double dx, dy, dz;    /* grid spacing (> 0), same unit as V dt */
+    int32_t sponge_width; /* W >= 0 cells on every face; 0 = no sponge */
+    double sponge_alpha;  /* g(d) = exp(-(alpha (W - d))^2) for distance d < W */
+    int32_t dtype;        /* WAVE_F32 */
+} wave_params_t;
+
+typedef struct wave_ctx wave_ctx;
+
+/* Host arithmetic only: layout of a field of interior size nx x ny x nz.
+ * Returns WAVE_EINVAL for sizes < 1, an unknown dtype, a NULL out, or a
+ * plane of 2^31 elements or more. */
+int wave_layout(int32_t nx, int32_t ny, int32_t nz, int32_t dtype, wave_layout_t *out);
+
+/*
+ * Create a context on the current device.
+ *   p         grid, spacing, sponge and storage type;
+ *   k         device, [layout] V^2 dt^2 per cell (interior read, ghosts ignored);
+ *   u_cur     device, [layout] u^n   (ghost cells zero);
+ *   u_prev    device, [layout] u^{n-1} (ghost cells zero); it is overwritten
+ *             by u^{n+1} in the first step (two time levels, paper Section IV-B);
+ *   src_zyx   host, 3 interior indices of the point source, or NULL for none;
+ *   rec_zyx   host, [nrec][3] interior indices of the receivers (may repeat);
+ *   nrec      >= 0;
+ *   stream    hipStream_t for all work of this context (NULL = default stream).
+ * Validates all arguments before touching the device (WAVE_EINVAL), builds
+ * the sponge profiles and receiver tables on the device, then reads k once
+ * and returns WAVE_EUNSTABLE if max(k) * (2048/315) * sum_a 1/h_a^2 > 4 or
+ * WAVE_EINVAL if k holds a negative or non-finite value (this read
+ * synchronises the stream).  The step counter starts at 0.  *out is owned
+ * by the library until wave_destroy.
+ */
+int wave_init(wave_ctx **out, const wave_params_t *p, const void *k, void *u_cur,
+              void *u_prev, const int32_t *src_zyx, const int32_t *rec_zyx, int32_t nrec,
+              void *stream);
+
+/* Attach a device trace buffer [nt_capacity][nrec] (FP32): the step with
+ * counter n writes row n.  NULL detaches.  Steps whose row would reach
+ * nt_capacity are rejected with WAVE_EINVAL before anything is enqueued. */
+int wave_record(wave_ctx *ctx, float *traces_dev, int32_t nt_capacity);
+
+/* Enqueue one step with source value src_value; the counter advances by 1
+ * and the two field buffers swap roles. */
+int wave_step(wave_ctx *ctx, float src_value);
+
+/* Enqueue nsteps >= 0 steps; step j (0-based within this call) adds
+ * src_dev[j] (device FP32 array of >= nsteps values), or nothing if
+ * src_dev is NULL. */
+int wave_run(wave_ctx *ctx, int32_t nsteps, const float *src_dev);
+
+/* Current roles: *cur holds u^n and *prev u^{n-1}, with n = *step.  Any
+ * output pointer may be NULL. */
+int wave_fields(const wave_ctx *ctx, void **cur, void **prev, int64_t *step);
+
+/* Reset the counter to 0 and the roles to those given at init (the caller
+ * re-initialises the field contents). */
+int wave_reset(wave_ctx *ctx);
+
+/* Replace the stream used by later calls. */
+int wave_set_stream(wave_ctx *ctx, void *stream);
+
+/*
+ * Kernel selection (tuning and cross-checks).  variant 0 = automatic;
+ * 1 .. wave_variant_count()-1 name compiled kernels (wave_variant_name);
+ * zchunk = planes per work-group along z (0 = automatic).  Takes effect
+ * from the next step; rebuilds the receiver tables.
+ */
+int wave_configure(wave_ctx *ctx, int32_t variant, int32_t zchunk);
+int32_t wave_variant_count(void);
+const char *wave_variant_name(int32_t variant);
+/* Variant and z-chunk in use, and the work-groups one step launches. */
+int wave_config(const wave_ctx *ctx, int32_t *variant, int32_t *zchunk, int32_t *workgroups);
+
+/* Wait for all work enqueued on the context's stream; WAVE_EHIP if it or
+ * any earlier launch failed. */
+int wave_sync(wave_ctx *ctx);
+
+/* Free library-owned memory (host and device); caller buffers are kept.
+ * NULL is accepted. */
+int wave_destroy(wave_ctx *ctx);
+
+const char *wave_strerror(int code);
+const char *wave_last_error(const wave_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WAVE_H */

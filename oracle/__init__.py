@@ -40,13 +40,10 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile oracle.c into liboracle.so with gcc (FP64, no fast-math,
-    no FMA contraction)."""
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SOURCE):
-        cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-               "-fPIC", "-shared", "-o", LIB_PATH + ".tmp", SOURCE, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    """Compile oracle.c into liboracle.so (see oracle/Makefile: gcc, FP64,
+    no fast-math, no FMA contraction)."""
+    cmd = ["make", "-s", "-C", _HERE] + (["-B"] if force else [])
+    subprocess.run(cmd, check=True)
     return LIB_PATH
 
 

@@ -1,0 +1,993 @@
+// libwave.so: single-precision time stepping of the 3-D acoustic wave
+// equation with the 25-point, 8th-order Laplacian inside a leapfrog update
+// (paper Section III: Eq. 2, the Laplacian and Algorithm 1), written for
+// MI355X (gfx950, CDNA4, wave64).  The C ABI is declared in include/wave.h.
+//
+// Kernel design.  The paper maps X and Y onto its processor grid and keeps
+// the whole Z column in each processor's memory (Section IV-B); a GPU has a
+// memory hierarchy instead, so the mapping here is the usual 2.5-D one:
+//   - a work-group owns an x-y tile and a range of z planes and marches
+//     through them;
+//   - each thread owns a float4 of 4 consecutive x cells in RY rows and
+//     keeps its z column z-4 .. z+4 in a 9-deep register queue (the GPU
+//     counterpart of the paper's z update from local memory, Section IV-C);
+//   - the centre plane of the tile, with a 4-cell halo in x and y, is
+//     staged in LDS (double buffered: one barrier per plane) and the x and
+//     y taps are read from there;
+//   - the next plane, the halo and u^{n-1}, k are prefetched one plane
+//     ahead so that HBM reads overlap the arithmetic;
+//   - sponge, source injection and receiver sampling are fused: the
+//     update, the source add and a per-work-group receiver epilogue happen
+//     in the same launch.
+// The step is bound by HBM bandwidth (about 3 flop per byte against a ridge
+// near 20 for FP32 vector math), so nothing here uses the matrix cores.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "wave.h"
+
+namespace {
+
+constexpr int kGhost = 4;
+constexpr int kXOffset = 32;   // interior x = 0 at element 32 of a row: 128-byte aligned
+constexpr int kPitchAlign = 32;
+
+// 8th-order central second-derivative weights (four points each way).
+constexpr double kC0 = -205.0 / 72.0;
+constexpr double kCm[4] = {8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+// max over wavenumbers of |c0 + 2 sum c_m cos(m kh)|, reached at kh = pi
+constexpr double kSymbolMax = 2048.0 / 315.0;
+
+struct alignas(16) f4 {
+    float v[4];
+};
+
+struct Coefs {
+    float ctr;    // c0 * (1/dx^2 + 1/dy^2 + 1/dz^2): the centre counted once
+    float cx[4];  // c_m / dx^2
+    float cy[4];
+    float cz[4];
+};
+
+struct StepArgs {
+    const float *__restrict__ k;
+    const float *__restrict__ cur;
+    float *nxt;  // holds u^{n-1} on entry, u^{n+1} on exit (same cells, same thread)
+    const float *__restrict__ gx;
+    const float *__restrict__ gy;
+    const float *__restrict__ gz;
+    Coefs c;
+    int nx, ny, nz;
+    int px;             // row pitch in elements
+    long long plane;    // elements per plane
+    int nxq;            // ceil(nx / 4): float4 columns holding interior cells
+    int ntx, nty, nchunks, zc, nwg;
+    int src_z, src_y, src_x;  // src_z < 0: no source
+    const float *src_ptr;     // device value of this step, or NULL
+    float src_val;            // used when src_ptr is NULL
+    const int *rec_start;     // [nwg + 1] receiver ranges per work-group
+    const long long *rec_off; // element offset of each receiver
+    const int *rec_idx;       // receiver number
+    float *trace_row;         // row of this step, or NULL
+};
+
+__device__ __forceinline__ float src_value(const StepArgs &a)
+{
+    return a.src_ptr ? a.src_ptr[0] : a.src_val;
+}
+
+// Element offset of interior (z, y, x) in the padded layout.
+__device__ __forceinline__ long long elem(const StepArgs &a, int z, int y, int x)
+{
+    return (long long)(z + kGhost) * a.plane + (long long)(y + kGhost) * a.px + kXOffset + x;
+}
+
+// Work-groups are handed to the 8 XCDs round-robin by block index; map
+// block b to logical work-group (b % 8) * (G / 8) + b / 8 so that each XCD
+// gets a contiguous run of neighbouring tiles whose halos share its L2.
+__device__ __forceinline__ int logical_wg()
+{
+    const int b = blockIdx.x;
+    const int per = gridDim.x >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+// Receiver epilogue: after the whole tile column is written, copy the
+// receivers this work-group owns into the trace row.
+__device__ __forceinline__ void sample_receivers(const StepArgs &a, int lid, int tid, int nt)
+{
+    if (!a.trace_row)
+        return;
+    const int r0 = a.rec_start[lid], r1 = a.rec_start[lid + 1];
+    if (r0 == r1)
+        return;
+    __syncthreads();
+    for (int i = r0 + tid; i < r1; i += nt)
+        a.trace_row[a.rec_idx[i]] = a.nxt[a.rec_off[i]];
+}
+
+// Raw buffer access.  A buffer resource covers one plane of one field; any
+// byte offset at or past its size reads as zero and drops stores, which is
+// how out-of-range tile cells are masked without branches.
+typedef unsigned u4raw __attribute__((vector_size(16)));
+constexpr int kRsrcWord3 = 0x00020000;  // 32-bit data format, raw (stride 0) access
+constexpr unsigned kOff = 0xffffffffu;  // an offset outside every resource
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float *field, long long plane_bytes,
+                                                            int z)
+{
+    const char *p = reinterpret_cast<const char *>(field) + (long long)(z + kGhost) * plane_bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), (short)0, (int)plane_bytes,
+                                             kRsrcWord3);
+}
+
+__device__ __forceinline__ f4 bload4(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    const u4raw v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    f4 o;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        o.v[e] = __uint_as_float(v[e]);
+    return o;
+}
+
+__device__ __forceinline__ void bstore4(__amdgpu_buffer_rsrc_t r, unsigned off, const f4 &v)
+{
+    u4raw w;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        w[e] = __float_as_uint(v.v[e]);
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, off, 0, 0);
+}
+
+__device__ __forceinline__ void bstore1(__amdgpu_buffer_rsrc_t r, unsigned off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+}
+
+template <int TXV, int TY, int RY>
+__global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
+{
+    constexpr int NT = TXV * TY;
+    constexpr int TYR = TY * RY;             // tile rows
+    constexpr int LW = TXV + 2;              // float4 per LDS row: one halo float4 each side
+    constexpr int LH = TYR + 8;              // LDS rows: 4 halo rows each side
+    constexpr int NH = 8 * TXV + 2 * TYR;    // halo float4 per plane
+    constexpr int HPT = (NH + NT - 1) / NT;  // halo float4 per thread
+    constexpr int QS = 10;                   // queue slots: 9 live planes + 1 being filled
+    __shared__ f4 lds[2][LH][LW];
+
+    const int lid = logical_wg();
+    if (lid >= a.nwg)
+        return;
+    const int tx = lid % a.ntx;
+    const int rest = lid / a.ntx;
+    const int ty = rest % a.nty;
+    const int ch = rest / a.nty;
+    const int z0 = ch * a.zc;
+    const int z1 = min(z0 + a.zc, a.nz);
+
+    const int tid = threadIdx.x;
+    const int lx = tid % TXV;
+    const int ly = tid / TXV;
+    const int xq0 = tx * TXV;          // first float4 column of the tile
+    const int y0 = ty * TYR;           // first row of the tile
+    const int xq = xq0 + lx;           // this thread's float4 column
+    const int x = 4 * xq;
+
+    // A float4 column may be read when it lies in [-1, nxq]: allocated and
+    // either interior, ghost or (beyond nx + 3) never used by an interior cell.
+    const bool col_load = xq <= a.nxq;
+    const bool col_interior = x < a.nx;
+    const bool col_full = x + 3 < a.nx;
+
+    // own rows: byte offsets within a plane (kOff when masked)
+    int row[RY];
+    bool row_int[RY];
+    unsigned own_ld[RY], own_in[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        row[r] = y0 + ly * RY + r;
+        row_int[r] = col_interior && row[r] < a.ny;
+        const unsigned b = 4u * unsigned((row[r] + kGhost) * a.px + kXOffset + x);
+        own_ld[r] = (col_load && row[r] < a.ny + kGhost) ? b : kOff;
+        own_in[r] = row_int[r] ? b : kOff;
+    }
+
+    // halo items of this thread
+    unsigned h_b[HPT];
+    int h_lds[HPT];  // flat LDS index (row * LW + col), -1 when unused
+#pragma unroll
+    for (int h = 0; h < HPT; ++h) {
+        const int i = tid + h * NT;
+        int hr, hc;
+        if (i < 8 * TXV) {
+            const int band = i / TXV;
+            hr = band < 4 ? band - 4 : TYR + band - 4;
+            hc = i % TXV;
+        } else {
+            const int j = i - 8 * TXV;
+            hr = j % TYR;
+            hc = (j / TYR) ? TXV : -1;
+        }
+        const bool use = i < NH;
+        h_lds[h] = use ? (hr + 4) * LW + (hc + 1) : -1;
+        const int gy = y0 + hr;
+        const int gq = xq0 + hc;
+        const bool ok = use && gy >= -kGhost && gy < a.ny + kGhost && gq >= -1 && gq <= a.nxq;
+        h_b[h] = ok ? 4u * unsigned((gy + kGhost) * a.px + kXOffset + 4 * gq) : kOff;
+    }
+
+    // sponge factors that do not change along z
+    f4 gxv = {{1.f, 1.f, 1.f, 1.f}};
+    if (col_interior) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            gxv.v[e] = (x + e < a.nx) ? a.gx[x + e] : 1.f;
+    }
+    float gyv[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+        gyv[r] = row_int[r] ? a.gy[row[r]] : 1.f;
+
+    // source ownership (the value is read once, before the march)
+    int src_r = -1, src_e = 0;
+    if (a.src_z >= z0 && a.src_z < z1 && (a.src_x >> 2) == xq) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+            if (row[r] == a.src_y)
+                src_r = r;
+        src_e = a.src_x & 3;
+    }
+    const float sval = src_r >= 0 ? src_value(a) : 0.f;
+
+    const long long pbytes = a.plane * (long long)sizeof(float);
+    const __amdgpu_buffer_rsrc_t gz_r = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float *>(a.gz), (short)0, a.nz * (int)sizeof(float), kRsrcWord3);
+
+    // register queue: at phase s the plane z - 4 + i lives in slot (s + i) % QS
+    f4 q[QS][RY];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const __amdgpu_buffer_rsrc_t rc = plane_rsrc(a.cur, pbytes, z0 - 4 + i);
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+            q[i][r] = bload4(rc, own_ld[r]);
+    }
+
+    // values of the next plane, loaded one plane ahead into the set of the
+    // other parity (no copies, so no wait before the next loads are issued)
+    f4 pv[2][RY], kv[2][RY], hv[2][HPT];
+    float gzv[2];
+    auto prefetch = [&](int z, int slot, int set) {
+        const __amdgpu_buffer_rsrc_t rq = plane_rsrc(a.cur, pbytes, z + 4);
+        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(a.nxt, pbytes, z);
+        const __amdgpu_buffer_rsrc_t rk = plane_rsrc(a.k, pbytes, z);
+        const __amdgpu_buffer_rsrc_t rh = plane_rsrc(a.cur, pbytes, z);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            q[slot][r] = bload4(rq, own_ld[r]);
+            pv[set][r] = bload4(rp, own_in[r]);
+            kv[set][r] = bload4(rk, own_in[r]);
+        }
+#pragma unroll
+        for (int h = 0; h < HPT; ++h)
+            hv[set][h] = bload4(rh, h_b[h]);
+        gzv[set] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(gz_r, 4u * z, 0, 0));
+    };
+    prefetch(z0, 8, 0);
+
+    const Coefs c = a.c;
+    for (int zb = z0; zb < z1; zb += QS) {
+#pragma unroll
+        for (int s = 0; s < QS; ++s) {
+            const int z = zb + s;
+            if (z >= z1)
+                break;
+            const int cur_set = s & 1;
+            // next plane (clamped on the last one, whose loads go unused)
+            prefetch(min(z + 1, z1 - 1), (s + 9) % QS, cur_set ^ 1);
+
+            const int b = z & 1;
+            f4 *L = &lds[b][0][0];
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+                L[(4 + ly * RY + r) * LW + lx + 1] = q[(s + 4) % QS][r];
+#pragma unroll
+            for (int h = 0; h < HPT; ++h)
+                if (h_lds[h] >= 0)
+                    L[h_lds[h]] = hv[cur_set][h];
+            __syncthreads();
+
+            // y taps: LDS rows ly*RY - 4 .. ly*RY + RY + 3 of this column,
+            // own rows straight from the queue
+            f4 ycol[RY + 8];
+#pragma unroll
+            for (int j = 0; j < RY + 8; ++j) {
+                if (j >= 4 && j < 4 + RY)
+                    ycol[j] = q[(s + 4) % QS][j - 4];
+                else
+                    ycol[j] = L[(ly * RY + j) * LW + lx + 1];
+            }
+
+            const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.nxt, pbytes, z);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                const f4 xl = L[(4 + ly * RY + r) * LW + lx];
+                const f4 xr = L[(4 + ly * RY + r) * LW + lx + 2];
+                const f4 ctr = q[(s + 4) % QS][r];
+                float xs[12];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    xs[e] = xl.v[e];
+                    xs[4 + e] = ctr.v[e];
+                    xs[8 + e] = xr.v[e];
+                }
+                f4 out;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float lap = c.ctr * ctr.v[e];
+#pragma unroll
+                    for (int m = 1; m <= 4; ++m) {
+                        lap = fmaf(c.cx[m - 1], xs[4 + e + m] + xs[4 + e - m], lap);
+                        lap = fmaf(c.cy[m - 1], ycol[4 + r + m].v[e] + ycol[4 + r - m].v[e], lap);
+                        lap = fmaf(c.cz[m - 1],
+                                   q[(s + 4 + m) % QS][r].v[e] + q[(s + 4 - m + QS) % QS][r].v[e],
+                                   lap);
+                    }
+                    const float g = gxv.v[e] * gyv[r] * gzv[cur_set];
+                    float t = fmaf(kv[cur_set][r].v[e], lap, 2.f * ctr.v[e]);
+                    t = fmaf(-g, pv[cur_set][r].v[e], t);
+                    out.v[e] = g * t;
+                }
+                if (src_r == r && z == a.src_z) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (e == src_e)
+                            out.v[e] += sval;
+                }
+                if (col_full) {
+                    bstore4(ro, own_in[r], out);
+                } else if (row_int[r]) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        bstore1(ro, x + e < a.nx ? own_in[r] + 4u * e : kOff, out.v[e]);
+                }
+            }
+        }
+    }
+
+    sample_receivers(a, lid, tid, NT);
+}
+
+// One thread per interior cell, every tap read from global memory: a
+// deliberately plain kernel used to cross-check the tiled one.
+__global__ __launch_bounds__(256) void step_naive(StepArgs a)
+{
+    const long long n = (long long)a.nx * a.ny * a.nz;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int x = (int)(i % a.nx);
+        const int y = (int)((i / a.nx) % a.ny);
+        const int z = (int)(i / ((long long)a.nx * a.ny));
+        const long long p = elem(a, z, y, x);
+        const float u = a.cur[p];
+        float lap = a.c.ctr * u;
+        for (int m = 1; m <= 4; ++m) {
+            lap = fmaf(a.c.cx[m - 1], a.cur[p + m] + a.cur[p - m], lap);
+            lap = fmaf(a.c.cy[m - 1], a.cur[p + (long long)m * a.px] + a.cur[p - (long long)m * a.px], lap);
+            lap = fmaf(a.c.cz[m - 1], a.cur[p + m * a.plane] + a.cur[p - m * a.plane], lap);
+        }
+        const float g = a.gx[x] * a.gy[y] * a.gz[z];
+        float t = fmaf(a.k[p], lap, 2.f * u);
+        t = fmaf(-g, a.nxt[p], t);
+        float v = g * t;
+        if (z == a.src_z && y == a.src_y && x == a.src_x)
+            v += src_value(a);
+        a.nxt[p] = v;
+    }
+}
+
+// Receivers for the naive kernel (separate launch: it has no tile epilogue).
+__global__ void sample_naive(const float *__restrict__ f, const long long *__restrict__ off,
+                             int nrec, float *row)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nrec)
+        row[r] = f[off[r]];
+}
+
+// Max, min and a non-finite flag of k over the interior, as float bit
+// patterns (valid for non-negative values; negatives raise the flag).
+__global__ __launch_bounds__(256) void k_range(const float *__restrict__ k, int nx, int ny, int nz,
+                                               int px, long long plane, unsigned *out)
+{
+    __shared__ unsigned smax[256], smin[256], sbad[256];
+    unsigned mx = 0u, mn = 0x7f800000u, bad = 0u;
+    const long long n = (long long)nx * ny * nz;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx);
+        const int y = (int)((i / nx) % ny);
+        const int z = (int)(i / ((long long)nx * ny));
+        const float v = k[(long long)(z + kGhost) * plane + (long long)(y + kGhost) * px + kXOffset + x];
+        if (!(v >= 0.f) || !(v < INFINITY)) {
+            bad = 1u;
+        } else {
+            const unsigned b = __float_as_uint(v);
+            mx = max(mx, b);
+            mn = min(mn, b);
+        }
+    }
+    const int t = threadIdx.x;
+    smax[t] = mx;
+    smin[t] = mn;
+    sbad[t] = bad;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) {
+            smax[t] = max(smax[t], smax[t + s]);
+            smin[t] = min(smin[t], smin[t + s]);
+            sbad[t] |= sbad[t + s];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        atomicMax(&out[0], smax[0]);
+        atomicMin(&out[1], smin[0]);
+        atomicOr(&out[2], sbad[0]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+typedef void (*StepKernel)(StepArgs);
+
+struct Variant {
+    const char *name;
+    StepKernel fn;  // NULL for the naive kernel
+    int txv, ty, ry;
+};
+
+const Variant kVariants[] = {
+    {"auto", nullptr, 0, 0, 0},
+    {"naive", nullptr, 0, 0, 0},
+    {"t64x16_r1", step_tiled<16, 16, 1>, 16, 16, 1},
+    {"t128x8_r1", step_tiled<32, 8, 1>, 32, 8, 1},
+    {"t128x16_r2", step_tiled<32, 8, 2>, 32, 8, 2},
+    {"t64x32_r2", step_tiled<16, 16, 2>, 16, 16, 2},
+    {"t128x16_r1", step_tiled<32, 16, 1>, 32, 16, 1},
+    {"t256x8_r2", step_tiled<64, 4, 2>, 64, 4, 2},
+    {"t64x16_r2", step_tiled<16, 8, 2>, 16, 8, 2},
+    {"t128x32_r4", step_tiled<32, 8, 4>, 32, 8, 4},
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+constexpr int kNaive = 1;
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+}  // namespace
+
+struct wave_ctx {
+    wave_params_t p;
+    wave_layout_t lay;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    const float *k = nullptr;
+    float *buf0 = nullptr, *buf1 = nullptr;  // roles at init: cur, prev
+    float *cur = nullptr, *prev = nullptr;
+    int64_t step = 0;
+    int src[3] = {-1, -1, -1};
+    std::vector<int32_t> rec;  // [nrec][3]
+    int nrec = 0;
+    float *traces = nullptr;
+    int32_t trace_cap = 0;
+    Coefs coefs{};
+    // device tables
+    float *gx = nullptr, *gy = nullptr, *gz = nullptr;
+    long long *rec_off_all = nullptr;  // receiver offsets in receiver order (naive sampling)
+    int *rec_start = nullptr;
+    long long *rec_off = nullptr;
+    int *rec_idx = nullptr;
+    int rec_start_len = 0;
+    // launch configuration
+    int variant = 0, zchunk = 0;  // requested (0 = auto)
+    int v_used = 0, zc_used = 0;
+    int ntx = 0, nty = 0, nchunks = 0, nwg = 0, grid = 0;
+    std::string err;
+};
+
+namespace {
+
+int fail(wave_ctx *ctx, int code, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return code;
+}
+
+#define HIP_TRY(ctx, call)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), WAVE_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));    \
+    } while (0)
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+void sponge_profile(int n, int width, double alpha, std::vector<float> &g)
+{
+    g.assign(n, 1.0f);
+    for (int i = 0; i < n; ++i) {
+        const int d = std::min(i, n - 1 - i);
+        if (d < width) {
+            const double t = alpha * double(width - d);
+            g[i] = float(std::exp(-t * t));
+        }
+    }
+}
+
+// Choose a variant and z-chunk; fill the grid geometry.
+void plan_launch(wave_ctx *c)
+{
+    const int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
+    int v = c->variant;
+    if (v == 0) {
+        const long long pts = (long long)nx * ny * nz;
+        v = pts >= (1ll << 22) ? 4 : 2;  // 128x16 tiles for large grids, 64x16 otherwise
+    }
+    c->v_used = v;
+    if (v == kNaive) {
+        c->ntx = c->nty = c->nchunks = 0;
+        c->zc_used = nz;
+        long long n = (long long)nx * ny * nz;
+        c->nwg = c->grid = int((n + 255) / 256);
+        return;
+    }
+    const Variant &V = kVariants[v];
+    const int tx = 4 * V.txv, tyr = V.ty * V.ry;
+    c->ntx = (nx + tx - 1) / tx;
+    c->nty = (ny + tyr - 1) / tyr;
+    const long long tiles = (long long)c->ntx * c->nty;
+    int zc = c->zchunk;
+    if (zc <= 0) {
+        // aim for >= 1024 work-groups (4 per CU on 256 CUs) with chunks >= 32 planes
+        long long want = (1024 + tiles - 1) / tiles;
+        zc = int((nz + want - 1) / want);
+        if (zc < 32)
+            zc = 32;
+    }
+    if (zc > nz)
+        zc = nz;
+    c->zc_used = zc;
+    c->nchunks = (nz + zc - 1) / zc;
+    c->nwg = int(tiles * c->nchunks);
+    c->grid = int(round_up(c->nwg, 8));
+}
+
+// Per-work-group receiver lists for the tiled kernels.
+int build_receiver_tables(wave_ctx *c)
+{
+    if (c->rec_start) {
+        (void)hipFree(c->rec_start);
+        c->rec_start = nullptr;
+    }
+    if (c->rec_off) {
+        (void)hipFree(c->rec_off);
+        c->rec_off = nullptr;
+    }
+    if (c->rec_idx) {
+        (void)hipFree(c->rec_idx);
+        c->rec_idx = nullptr;
+    }
+    if (c->v_used == kNaive)
+        return WAVE_OK;
+    const Variant &V = kVariants[c->v_used];
+    const int tx = 4 * V.txv, tyr = V.ty * V.ry;
+    std::vector<int> start(c->nwg + 1, 0), owner(c->nrec);
+    for (int r = 0; r < c->nrec; ++r) {
+        const int z = c->rec[3 * r], y = c->rec[3 * r + 1], x = c->rec[3 * r + 2];
+        const int lid = ((z / c->zc_used) * c->nty + y / tyr) * c->ntx + x / tx;
+        owner[r] = lid;
+        start[lid + 1]++;
+    }
+    for (int i = 0; i < c->nwg; ++i)
+        start[i + 1] += start[i];
+    std::vector<int> fill(start.begin(), start.end() - 1), idx(std::max(c->nrec, 1));
+    std::vector<long long> off(std::max(c->nrec, 1));
+    for (int r = 0; r < c->nrec; ++r) {
+        const int z = c->rec[3 * r], y = c->rec[3 * r + 1], x = c->rec[3 * r + 2];
+        const int slot = fill[owner[r]]++;
+        idx[slot] = r;
+        off[slot] = ((long long)(z + kGhost) * c->lay.rows + (y + kGhost)) * c->lay.pitch_x +
+                    kXOffset + x;
+    }
+    HIP_TRY(c, hipMalloc(&c->rec_start, sizeof(int) * start.size()));
+    HIP_TRY(c, hipMalloc(&c->rec_off, sizeof(long long) * off.size()));
+    HIP_TRY(c, hipMalloc(&c->rec_idx, sizeof(int) * idx.size()));
+    HIP_TRY(c, hipMemcpy(c->rec_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->rec_off, off.data(), sizeof(long long) * off.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->rec_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice));
+    c->rec_start_len = int(start.size());
+    return WAVE_OK;
+}
+
+int launch_step(wave_ctx *c, const float *src_ptr, float src_val)
+{
+    StepArgs a;
+    a.k = c->k;
+    a.cur = c->cur;
+    a.nxt = c->prev;
+    a.gx = c->gx;
+    a.gy = c->gy;
+    a.gz = c->gz;
+    a.c = c->coefs;
+    a.nx = c->p.nx;
+    a.ny = c->p.ny;
+    a.nz = c->p.nz;
+    a.px = int(c->lay.pitch_x);
+    a.plane = c->lay.plane;
+    a.nxq = (c->p.nx + 3) / 4;
+    a.ntx = c->ntx;
+    a.nty = c->nty;
+    a.nchunks = c->nchunks;
+    a.zc = c->zc_used;
+    a.nwg = c->nwg;
+    a.src_z = c->src[0];
+    a.src_y = c->src[1];
+    a.src_x = c->src[2];
+    a.src_ptr = src_ptr;
+    a.src_val = src_val;
+    a.rec_start = c->rec_start;
+    a.rec_off = c->rec_off;
+    a.rec_idx = c->rec_idx;
+    a.trace_row = (c->traces && c->nrec > 0) ? c->traces + (size_t)c->step * c->nrec : nullptr;
+
+    if (c->v_used == kNaive) {
+        hipLaunchKernelGGL(step_naive, dim3(c->grid), dim3(256), 0, c->stream, a);
+        if (a.trace_row)
+            hipLaunchKernelGGL(sample_naive, dim3((c->nrec + 255) / 256), dim3(256), 0, c->stream,
+                               (const float *)c->prev, (const long long *)c->rec_off_all, c->nrec,
+                               a.trace_row);
+    } else {
+        const Variant &V = kVariants[c->v_used];
+        hipLaunchKernelGGL(V.fn, dim3(c->grid), dim3(V.txv * V.ty), 0, c->stream, a);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(c, WAVE_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+    // u^{n+1} now lives in the old u^{n-1} buffer
+    float *t = c->prev;
+    c->prev = c->cur;
+    c->cur = t;
+    c->step += 1;
+    return WAVE_OK;
+}
+
+int check_trace_room(wave_ctx *c, int64_t nsteps)
+{
+    if (c->traces && c->nrec > 0 && c->step + nsteps > c->trace_cap)
+        return fail(c, WAVE_EINVAL, "trace buffer holds %d rows; steps %lld..%lld requested",
+                    c->trace_cap, (long long)c->step, (long long)(c->step + nsteps - 1));
+    return WAVE_OK;
+}
+
+void free_device(wave_ctx *c)
+{
+    float **fs[] = {&c->gx, &c->gy, &c->gz};
+    for (float **f : fs)
+        if (*f) {
+            (void)hipFree(*f);
+            *f = nullptr;
+        }
+    if (c->rec_off_all) {
+        (void)hipFree(c->rec_off_all);
+        c->rec_off_all = nullptr;
+    }
+    if (c->rec_start) {
+        (void)hipFree(c->rec_start);
+        c->rec_start = nullptr;
+    }
+    if (c->rec_off) {
+        (void)hipFree(c->rec_off);
+        c->rec_off = nullptr;
+    }
+    if (c->rec_idx) {
+        (void)hipFree(c->rec_idx);
+        c->rec_idx = nullptr;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int wave_layout(int32_t nx, int32_t ny, int32_t nz, int32_t dtype, wave_layout_t *out)
+{
+    if (!out || nx < 1 || ny < 1 || nz < 1 || dtype != WAVE_F32)
+        return WAVE_EINVAL;
+    wave_layout_t l;
+    const int64_t nxq = (nx + 3) / 4;
+    l.x_offset = kXOffset;
+    l.pitch_x = round_up(kXOffset + 4 * nxq + 4, kPitchAlign);
+    l.rows = int64_t(ny) + 2 * kGhost;
+    l.planes = int64_t(nz) + 2 * kGhost;
+    l.plane = l.pitch_x * l.rows;
+    if (l.plane >= (int64_t(1) << 31))
+        return WAVE_EINVAL;
+    l.elems = l.plane * l.planes;
+    l.bytes = l.elems * int64_t(sizeof(float));
+    *out = l;
+    return WAVE_OK;
+}
+
+int wave_init(wave_ctx **out, const wave_params_t *p, const void *k, void *u_cur, void *u_prev,
+              const int32_t *src_zyx, const int32_t *rec_zyx, int32_t nrec, void *stream)
+{
+    if (!out)
+        return WAVE_EINVAL;
+    *out = nullptr;
+    if (!p || !k || !u_cur || !u_prev || u_cur == u_prev || nrec < 0 || (nrec > 0 && !rec_zyx))
+        return WAVE_EINVAL;
+    // float4 accesses need 16-byte aligned fields
+    if ((reinterpret_cast<uintptr_t>(k) | reinterpret_cast<uintptr_t>(u_cur) |
+         reinterpret_cast<uintptr_t>(u_prev)) & 15u)
+        return WAVE_EINVAL;
+    wave_layout_t lay;
+    if (wave_layout(p->nx, p->ny, p->nz, p->dtype, &lay) != WAVE_OK)
+        return WAVE_EINVAL;
+    if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->dz))
+        return WAVE_EINVAL;
+    if (p->sponge_width < 0 || !std::isfinite(p->sponge_alpha) || p->sponge_alpha < 0.0)
+        return WAVE_EINVAL;
+    const int dims[3] = {p->nz, p->ny, p->nx};
+    if (src_zyx)
+        for (int a = 0; a < 3; ++a)
+            if (src_zyx[a] < 0 || src_zyx[a] >= dims[a])
+                return WAVE_EINVAL;
+    for (int32_t r = 0; r < nrec; ++r)
+        for (int a = 0; a < 3; ++a)
+            if (rec_zyx[3 * r + a] < 0 || rec_zyx[3 * r + a] >= dims[a])
+                return WAVE_EINVAL;
+
+    wave_ctx *c = new (std::nothrow) wave_ctx();
+    if (!c)
+        return WAVE_ENOMEM;
+    c->p = *p;
+    c->lay = lay;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->k = static_cast<const float *>(k);
+    c->buf0 = c->cur = static_cast<float *>(u_cur);
+    c->buf1 = c->prev = static_cast<float *>(u_prev);
+    if (src_zyx)
+        for (int a = 0; a < 3; ++a)
+            c->src[a] = src_zyx[a];
+    c->nrec = nrec;
+    c->rec.assign(rec_zyx, rec_zyx + 3 * (size_t)nrec);
+
+    const double ih2[3] = {1.0 / (p->dx * p->dx), 1.0 / (p->dy * p->dy), 1.0 / (p->dz * p->dz)};
+    c->coefs.ctr = float(kC0 * (ih2[0] + ih2[1] + ih2[2]));
+    for (int m = 0; m < 4; ++m) {
+        c->coefs.cx[m] = float(kCm[m] * ih2[0]);
+        c->coefs.cy[m] = float(kCm[m] * ih2[1]);
+        c->coefs.cz[m] = float(kCm[m] * ih2[2]);
+    }
+
+    auto bail = [&](int code) {
+        free_device(c);
+        delete c;
+        return code;
+    };
+    if (hipGetDevice(&c->device) != hipSuccess)
+        return bail(WAVE_EHIP);
+
+    // sponge profiles
+    std::vector<float> g;
+    float **dst[3] = {&c->gx, &c->gy, &c->gz};
+    const int n3[3] = {p->nx, p->ny, p->nz};
+    for (int a = 0; a < 3; ++a) {
+        sponge_profile(n3[a], p->sponge_width, p->sponge_alpha, g);
+        if (hipMalloc(dst[a], sizeof(float) * g.size()) != hipSuccess)
+            return bail(WAVE_ENOMEM);
+        if (hipMemcpy(*dst[a], g.data(), sizeof(float) * g.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(WAVE_EHIP);
+    }
+    // receiver offsets in receiver order
+    {
+        std::vector<long long> off(std::max(nrec, 1));
+        for (int r = 0; r < nrec; ++r)
+            off[r] = ((long long)(c->rec[3 * r] + kGhost) * lay.rows + (c->rec[3 * r + 1] + kGhost)) *
+                         lay.pitch_x + kXOffset + c->rec[3 * r + 2];
+        if (hipMalloc(&c->rec_off_all, sizeof(long long) * off.size()) != hipSuccess)
+            return bail(WAVE_ENOMEM);
+        if (hipMemcpy(c->rec_off_all, off.data(), sizeof(long long) * off.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(WAVE_EHIP);
+    }
+    plan_launch(c);
+    if (build_receiver_tables(c) != WAVE_OK)
+        return bail(WAVE_EHIP);
+
+    // stability: max(k) * symbol_max * sum 1/h^2 <= 4
+    unsigned *d = nullptr;
+    unsigned init[3] = {0u, 0x7f800000u, 0u}, res[3];
+    if (hipMalloc(&d, sizeof(init)) != hipSuccess)
+        return bail(WAVE_ENOMEM);
+    bool ok = hipMemcpyAsync(d, init, sizeof(init), hipMemcpyHostToDevice, c->stream) == hipSuccess;
+    if (ok) {
+        hipLaunchKernelGGL(k_range, dim3(1024), dim3(256), 0, c->stream, c->k, p->nx, p->ny, p->nz,
+                           int(lay.pitch_x), (long long)lay.plane, d);
+        ok = hipGetLastError() == hipSuccess &&
+             hipMemcpyAsync(res, d, sizeof(res), hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
+             hipStreamSynchronize(c->stream) == hipSuccess;
+    }
+    (void)hipFree(d);
+    if (!ok)
+        return bail(WAVE_EHIP);
+    if (res[2])
+        return bail(WAVE_EINVAL);
+    float kmax;
+    std::memcpy(&kmax, &res[0], sizeof(float));
+    if (double(kmax) * kSymbolMax * (ih2[0] + ih2[1] + ih2[2]) > 4.0)
+        return bail(WAVE_EUNSTABLE);
+
+    *out = c;
+    return WAVE_OK;
+}
+
+int wave_record(wave_ctx *ctx, float *traces_dev, int32_t nt_capacity)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    if (traces_dev && nt_capacity < 0)
+        return fail(ctx, WAVE_EINVAL, "negative trace capacity");
+    ctx->traces = traces_dev;
+    ctx->trace_cap = traces_dev ? nt_capacity : 0;
+    return WAVE_OK;
+}
+
+int wave_step(wave_ctx *ctx, float src_value)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    int rc = check_trace_room(ctx, 1);
+    if (rc != WAVE_OK)
+        return rc;
+    return launch_step(ctx, nullptr, src_value);
+}
+
+int wave_run(wave_ctx *ctx, int32_t nsteps, const float *src_dev)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    if (nsteps < 0)
+        return fail(ctx, WAVE_EINVAL, "nsteps < 0");
+    int rc = check_trace_room(ctx, nsteps);
+    if (rc != WAVE_OK)
+        return rc;
+    for (int32_t j = 0; j < nsteps; ++j) {
+        rc = launch_step(ctx, src_dev ? src_dev + j : nullptr, 0.0f);
+        if (rc != WAVE_OK)
+            return rc;
+    }
+    return WAVE_OK;
+}
+
+int wave_fields(const wave_ctx *ctx, void **cur, void **prev, int64_t *step)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    if (cur)
+        *cur = ctx->cur;
+    if (prev)
+        *prev = ctx->prev;
+    if (step)
+        *step = ctx->step;
+    return WAVE_OK;
+}
+
+int wave_reset(wave_ctx *ctx)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    ctx->cur = ctx->buf0;
+    ctx->prev = ctx->buf1;
+    ctx->step = 0;
+    return WAVE_OK;
+}
+
+int wave_set_stream(wave_ctx *ctx, void *stream)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    return WAVE_OK;
+}
+
+int wave_configure(wave_ctx *ctx, int32_t variant, int32_t zchunk)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    if (variant < 0 || variant >= kNumVariants || zchunk < 0)
+        return fail(ctx, WAVE_EINVAL, "unknown variant %d or negative z-chunk %d", variant, zchunk);
+    ctx->variant = variant;
+    ctx->zchunk = zchunk;
+    plan_launch(ctx);
+    return build_receiver_tables(ctx);
+}
+
+int32_t wave_variant_count(void) { return kNumVariants; }
+
+const char *wave_variant_name(int32_t variant)
+{
+    if (variant < 0 || variant >= kNumVariants)
+        return nullptr;
+    return kVariants[variant].name;
+}
+
+int wave_config(const wave_ctx *ctx, int32_t *variant, int32_t *zchunk, int32_t *workgroups)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    if (variant)
+        *variant = ctx->v_used;
+    if (zchunk)
+        *zchunk = ctx->zc_used;
+    if (workgroups)
+        *workgroups = ctx->nwg;
+    return WAVE_OK;
+}
+
+int wave_sync(wave_ctx *ctx)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, hipGetLastError());
+    return WAVE_OK;
+}
+
+int wave_destroy(wave_ctx *ctx)
+{
+    if (!ctx)
+        return WAVE_OK;
+    free_device(ctx);
+    delete ctx;
+    return WAVE_OK;
+}
+
+const char *wave_strerror(int code)
+{
+    switch (code) {
+    case WAVE_OK: return "ok";
+    case WAVE_EINVAL: return "invalid argument";
+    case WAVE_EUNSTABLE: return "time step violates the leapfrog stability limit";
+    case WAVE_ESTATE: return "invalid state";
+    case WAVE_ENOMEM: return "out of memory";
+    case WAVE_EHIP: return "HIP runtime error";
+    default: return "unknown error";
+    }
+}
+
+const char *wave_last_error(const wave_ctx *ctx)
+{
+    if (!ctx)
+        return "";
+    return ctx->err.c_str();
+}
+
+}  // extern "C"

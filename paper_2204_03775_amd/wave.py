@@ -1,0 +1,293 @@
+"""ctypes binding of libwave.so (C ABI in include/wave.h).
+
+Argument marshalling only: every step of the propagator runs in the HIP
+kernels of libwave.so.  PyTorch supplies device memory and streams.  The
+functions carry the C names; ``Propagator`` bundles the allocation of the
+padded fields and the context for convenience.
+
+The library must be built (``__graft_entry__.build()``); importing this
+module raises ``ImportError`` if it is missing, so nothing can silently fall
+back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime libwave.so resolves against (same soname)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwave.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "wave.h")
+
+WAVE_OK = 0
+WAVE_EINVAL = -1
+WAVE_EUNSTABLE = -2
+WAVE_ESTATE = -3
+WAVE_ENOMEM = -4
+WAVE_EHIP = -5
+WAVE_F32 = 0
+
+GHOST = 4
+
+
+class WaveError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{message} (code {code})")
+        self.code = code
+
+
+class wave_layout_t(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("pitch_x", "rows", "planes", "x_offset", "plane", "elems", "bytes")]
+
+
+class wave_params_t(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("sponge_width", ctypes.c_int32), ("sponge_alpha", ctypes.c_double),
+                ("dtype", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    ci = ctypes.c_int
+    sig = {
+        "wave_layout": ([i32, i32, i32, i32, ctypes.POINTER(wave_layout_t)], ci),
+        "wave_init": ([ctypes.POINTER(vp), ctypes.POINTER(wave_params_t), vp, vp, vp,
+                       ctypes.POINTER(i32), ctypes.POINTER(i32), i32, vp], ci),
+        "wave_record": ([vp, vp, i32], ci),
+        "wave_step": ([vp, f32], ci),
+        "wave_run": ([vp, i32, vp], ci),
+        "wave_fields": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64)], ci),
+        "wave_reset": ([vp], ci),
+        "wave_set_stream": ([vp, vp], ci),
+        "wave_configure": ([vp, i32, i32], ci),
+        "wave_variant_count": ([], i32),
+        "wave_variant_name": ([i32], ctypes.c_char_p),
+        "wave_config": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], ci),
+        "wave_sync": ([vp], ci),
+        "wave_destroy": ([vp], ci),
+        "wave_strerror": ([ci], ctypes.c_char_p),
+        "wave_last_error": ([vp], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(rc: int, ctx=None):
+    if rc != WAVE_OK:
+        msg = _lib.wave_strerror(rc).decode()
+        if ctx:
+            detail = _lib.wave_last_error(ctx).decode()
+            if detail:
+                msg = f"{msg}: {detail}"
+        raise WaveError(rc, msg)
+
+
+# --- the C functions, one for one -------------------------------------------
+
+def wave_layout(nx: int, ny: int, nz: int, dtype: int = WAVE_F32) -> wave_layout_t:
+    out = wave_layout_t()
+    _check(_lib.wave_layout(nx, ny, nz, dtype, ctypes.byref(out)))
+    return out
+
+
+def _zyx_array(pts):
+    import numpy as np
+
+    a = np.ascontiguousarray(np.asarray(pts, dtype=np.int32).reshape(-1, 3))
+    return a, (ctypes.c_int32 * a.size)(*a.ravel().tolist())
+
+
+def wave_init(params: wave_params_t, k_ptr: int, cur_ptr: int, prev_ptr: int, src=None,
+              rec=None, stream: int | None = None):
+    ctx = ctypes.c_void_p()
+    src_buf = (ctypes.c_int32 * 3)(*[int(v) for v in src]) if src is not None else None
+    nrec = 0
+    rec_buf = None
+    if rec is not None:
+        arr, rec_buf = _zyx_array(rec)
+        nrec = arr.shape[0]
+        if nrec == 0:
+            rec_buf = None
+    rc = _lib.wave_init(ctypes.byref(ctx), ctypes.byref(params), k_ptr, cur_ptr, prev_ptr,
+                        src_buf, rec_buf, nrec, stream)
+    _check(rc)
+    return ctx
+
+
+def wave_record(ctx, traces_ptr, nt_capacity: int):
+    _check(_lib.wave_record(ctx, traces_ptr, nt_capacity), ctx)
+
+
+def wave_step(ctx, src_value: float):
+    _check(_lib.wave_step(ctx, src_value), ctx)
+
+
+def wave_run(ctx, nsteps: int, src_ptr=None):
+    _check(_lib.wave_run(ctx, nsteps, src_ptr), ctx)
+
+
+def wave_fields(ctx):
+    cur, prev, step = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64()
+    _check(_lib.wave_fields(ctx, ctypes.byref(cur), ctypes.byref(prev), ctypes.byref(step)), ctx)
+    return cur.value, prev.value, step.value
+
+
+def wave_reset(ctx):
+    _check(_lib.wave_reset(ctx), ctx)
+
+
+def wave_set_stream(ctx, stream):
+    _check(_lib.wave_set_stream(ctx, stream), ctx)
+
+
+def wave_configure(ctx, variant: int = 0, zchunk: int = 0):
+    _check(_lib.wave_configure(ctx, variant, zchunk), ctx)
+
+
+def wave_variant_count() -> int:
+    return _lib.wave_variant_count()
+
+
+def wave_variant_name(v: int):
+    r = _lib.wave_variant_name(v)
+    return r.decode() if r is not None else None
+
+
+def wave_config(ctx):
+    v, zc, wg = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.wave_config(ctx, ctypes.byref(v), ctypes.byref(zc), ctypes.byref(wg)), ctx)
+    return v.value, zc.value, wg.value
+
+
+def wave_sync(ctx):
+    _check(_lib.wave_sync(ctx), ctx)
+
+
+def wave_destroy(ctx):
+    _check(_lib.wave_destroy(ctx))
+
+
+def wave_strerror(code: int) -> str:
+    return _lib.wave_strerror(code).decode()
+
+
+def wave_last_error(ctx) -> str:
+    return _lib.wave_last_error(ctx).decode()
+
+
+def variants() -> dict:
+    return {wave_variant_name(i): i for i in range(wave_variant_count())}
+
+
+# --- convenience wrapper ----------------------------------------------------
+
+class Propagator:
+    """Fields in the library's padded layout (torch tensors on the current
+    device) plus a context.  ``k`` is a dense [nz][ny][nx] array (numpy or
+    torch) of V^2 dt^2, rounded to FP32 once."""
+
+    def __init__(self, nx, ny, nz, h, k, *, src=None, rec=None, sponge_width=0,
+                 sponge_alpha=0.0, stream=None, device=None):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.h = tuple(float(v) for v in h)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.layout = wave_layout(self.nx, self.ny, self.nz)
+        n = self.layout.elems
+        self.k = torch.zeros(n, dtype=torch.float32, device=self.device)
+        self.buf = [torch.zeros(n, dtype=torch.float32, device=self.device),
+                    torch.zeros(n, dtype=torch.float32, device=self.device)]
+        self.interior(self.k).copy_(torch.as_tensor(k).to(device=self.device, dtype=torch.float32))
+        self.src = tuple(int(v) for v in src) if src is not None else None
+        self.rec = rec
+        self.nrec = 0 if rec is None else len(rec)
+        p = wave_params_t(self.nx, self.ny, self.nz, self.h[0], self.h[1], self.h[2],
+                          int(sponge_width), float(sponge_alpha), WAVE_F32)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = wave_init(p, self.k.data_ptr(), self.buf[0].data_ptr(), self.buf[1].data_ptr(),
+                             self.src, rec, self.stream.cuda_stream)
+        self.traces = None
+
+    # layout helpers (views, no copies)
+    def padded(self, buf):
+        L = self.layout
+        return buf.view(L.planes, L.rows, L.pitch_x)
+
+    def interior(self, buf):
+        L = self.layout
+        x0 = L.x_offset
+        return self.padded(buf)[GHOST:GHOST + self.nz, GHOST:GHOST + self.ny, x0:x0 + self.nx]
+
+    def _by_ptr(self, ptr):
+        for b in self.buf:
+            if b.data_ptr() == ptr:
+                return b
+        raise RuntimeError("library reported an unknown field pointer")
+
+    def fields(self):
+        """(u^n, u^{n-1}, n): padded tensors in their current roles."""
+        cur, prev, step = wave_fields(self.ctx)
+        return self._by_ptr(cur), self._by_ptr(prev), step
+
+    def record(self, nt_capacity: int):
+        self.traces = torch.zeros((nt_capacity, max(self.nrec, 1)), dtype=torch.float32,
+                                  device=self.device)
+        wave_record(self.ctx, self.traces.data_ptr(), nt_capacity)
+        return self.traces
+
+    def step(self, src_value: float = 0.0):
+        wave_step(self.ctx, float(src_value))
+
+    def run(self, nsteps: int, src=None):
+        """``src``: device FP32 tensor with >= nsteps values, or None."""
+        ptr = None
+        if src is not None:
+            assert src.dtype == torch.float32 and src.is_cuda and src.is_contiguous()
+            assert src.numel() >= nsteps
+            ptr = src.data_ptr()
+        wave_run(self.ctx, int(nsteps), ptr)
+
+    def configure(self, variant=0, zchunk=0):
+        if isinstance(variant, str):
+            variant = variants()[variant]
+        wave_configure(self.ctx, variant, zchunk)
+
+    def config(self):
+        return wave_config(self.ctx)
+
+    def reset(self, zero_fields: bool = True):
+        wave_reset(self.ctx)
+        if zero_fields:
+            for b in self.buf:
+                b.zero_()
+            if self.traces is not None:
+                self.traces.zero_()
+
+    def sync(self):
+        wave_sync(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            wave_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
