@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Throughput of the FP32 25-point leapfrog propagator on one MI355X.
+
+One benchmark step is one complete shot of the large-shot workload: the
+fields are cleared and 1000 time steps of 512^3 are run (source injection,
+sponge and 256 receivers fused into every step).  Inputs are resident in
+HBM before timing starts.  The JSON line on stdout carries:
+
+  value      interior grid-point updates per second (Gpts/s) over the timed
+             shots, wall clock between two device synchronisations;
+  roofline   the step kernel against the 8 TB/s HBM peak: 16 algorithmic
+             bytes per update (read u^n, u^{n-1}, k; write u^{n+1}) divided
+             by its average launch time from HIP events on its stream;
+             `traffic` is the HBM byte count per launch measured with
+             rocprofv3 counters (profiles/), reported only while the kernel
+             source matches the one profiled;
+  cpu_baseline  the FP64 CPU oracle on the first steps of the same shot.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "large_shot": "512^3 x 1000 steps FP32, dx=10 m, dt=0.8 CFL at 4500 m/s, 5 layers "
+                  "1500-4500 m/s x (1+0.05 p) smoothed noise, 20-cell sponge, 12 Hz Ricker "
+                  "at z=25, 256 receivers on a line (synthetic, seeded)",
+    "small_parity": "64^3 x 100 steps FP32, v=1500 m/s, dt=1 ms, 15 Hz Ricker at the "
+                    "centre, 16 random receivers, zero ghost layer (synthetic, seeded)",
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_large_shot.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2204_03775_amd", "csrc", "wave.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_digest() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel_name: str, zchunk: int):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source and launch configuration."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if (t.get("source_sha256") != source_digest() or t.get("kernel") != kernel_name
+            or t.get("zchunk") != zchunk):
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(p, target_seconds: float):
+    """The FP64 oracle, as it stands, on the first steps of the same shot."""
+    import oracle
+
+    threads = oracle.default_threads()
+    k64 = p.k64()
+    kw = dict(s=p.s, src=p.src, rec=p.rec, sponge_width=p.sponge_width,
+              sponge_alpha=p.sponge_alpha, nthreads=threads)
+    t = time.perf_counter()
+    oracle.run(k64, p.h, 1, **kw)
+    one = time.perf_counter() - t
+    n = int(max(2, min(50, round(target_seconds / max(one, 1e-3)))))
+    t = time.perf_counter()
+    oracle.run(k64, p.h, n, **kw)
+    sec = time.perf_counter() - t
+    return {"value": round(p.points * n / sec / 1e9, 4), "unit": "Gpts/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {n} of the {p.nt} steps of the same {p.nx}x{p.ny}x{p.nz} shot, "
+                      f"FP64, {sec:.1f} s, OpenMP threads={threads}, "
+                      f"cpu={_cpu_model()}"}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed shots")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed shots before timing")
+    ap.add_argument("--workload", default="large_shot", choices=sorted(WORKLOADS))
+    ap.add_argument("--variant", default="auto", help="kernel variant name (auto = library choice)")
+    ap.add_argument("--zchunk", type=int, default=0, help="z planes per work-group (0 = auto)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        log(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this "
+            "build (the propagator is single-GPU; multi-GPU sharding is a design note only).")
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2204_03775_amd import inputs, metrics, wave
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    t = time.perf_counter()
+    p = getattr(inputs, args.workload)()
+    log(f"workload {args.workload}: {p.nx}x{p.ny}x{p.nz} x {p.nt} steps "
+        f"(generated in {time.perf_counter() - t:.1f} s)")
+
+    prop = wave.Propagator(p.nx, p.ny, p.nz, p.h, p.k32(), src=p.src, rec=p.rec,
+                           sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+    prop.configure(args.variant, args.zchunk)
+    variant, zchunk, nwg = prop.config()
+    kname = wave.wave_variant_name(variant)
+    log(f"kernel {kname}, z-chunk {zchunk}, {nwg} work-groups per step")
+    prop.record(p.nt)
+    s = torch.tensor(p.s, dtype=torch.float32, device="cuda")
+    stream = prop.stream
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+
+    def shot(i=None):
+        prop.reset()
+        if i is not None:
+            starts[i].record(stream)
+        prop.run(p.nt, s)
+        if i is not None:
+            ends[i].record(stream)
+
+    for _ in range(args.warmup):
+        shot()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        shot(i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prop.sync()
+
+    kernel_s = sum(a.elapsed_time(b) for a, b in zip(starts, ends)) / 1e3 / (args.steps * p.nt)
+    cur, _, _ = prop.fields()
+    field = prop.interior(cur)
+    tr = prop.traces[:, :prop.nrec]
+    ok = bool(torch.isfinite(field).all().item() and torch.isfinite(tr).all().item()
+              and tr.abs().max().item() > 0)
+    if not ok:
+        log("error: non-finite or empty result")
+        return 1
+
+    gpts = metrics.gpts_per_s(p.nx, p.ny, p.nz, p.nt * args.steps, wall)
+    launch_bytes = metrics.BYTES_PER_POINT_F32 * p.points
+    achieved = launch_bytes / kernel_s / 1e9
+    traffic = measured_traffic(kname, zchunk) if args.workload == "large_shot" else None
+    log(f"{gpts:.1f} Gpts/s wall, kernel {kernel_s * 1e6:.1f} us/launch = {achieved:.0f} GB/s "
+        f"({achieved / metrics.MI355X_HBM_PEAK_GBS:.3f} of peak), paper-convention "
+        f"{metrics.paper_tflops(gpts):.1f} TFLOP/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(p, args.cpu_seconds)
+        log(f"oracle: {cpu['value']} Gpts/s ({cpu['sample']})")
+
+    rec = {
+        "metric": "Gpts/s stencil updates + % HBM roofline (FP32 vs FP16-store); shots/s",
+        "value": round(gpts, 3),
+        "unit": "Gpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
+                   "nx": p.nx, "ny": p.ny, "nz": p.nz, "time_steps": p.nt,
+                   "kernel": kname, "zchunk": zchunk, "workgroups": nwg,
+                   "shots_per_s": round(args.steps / wall, 4),
+                   "paper_tflops_51flop": round(metrics.paper_tflops(gpts), 2),
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": metrics.MI355X_HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / metrics.MI355X_HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+    }
+    prop.close()
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
