@@ -1,0 +1,32 @@
+/*
+ * wave_probe.h -- bandwidth probes shipped beside libwave.so (libwave_probe.so).
+ *
+ * Not part of the propagator: plain streaming kernels of known traffic,
+ * used to measure the HBM bandwidth this GPU actually sustains for the
+ * propagator's access pattern and to calibrate hardware byte counters.
+ * All pointers are device pointers of n floats (16-byte aligned, n a
+ * multiple of 4); work is enqueued on `stream` and not waited for.
+ * Return 0, or -1 for bad arguments / -5 for a failed launch.
+ */
+#ifndef WAVE_PROBE_H
+#define WAVE_PROBE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* dst[i] = src[i]: 8 bytes of HBM traffic per element. */
+int probe_copy(const float *src, float *dst, int64_t n, void *stream);
+
+/* d[i] = a[i] + b[i] + c[i]: three reads and one write per element (16 bytes),
+ * the access mix of one propagator update. */
+int probe_read3_write1(const float *a, const float *b, const float *c, float *d, int64_t n,
+                       void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WAVE_PROBE_H */
