@@ -24,6 +24,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -129,9 +130,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float *field,
                                              kRsrcWord3);
 }
 
+// Cache policy of a buffer access (gfx950 encoding of the aux operand):
+// bit 1 = non-temporal.  u^{n-1} and k are read exactly once per step and
+// u^{n+1} is not read again in the step, so they are streamed
+// non-temporally; u^n is read by the neighbouring tiles as their halo and
+// keeps the default policy, so it stays resident in L2.
+constexpr int kKeep = 0;
+constexpr int kStream = 2;
+
+template <int POL>
 __device__ __forceinline__ f4 bload4(__amdgpu_buffer_rsrc_t r, unsigned off)
 {
-    const u4raw v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    const u4raw v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, POL);
     f4 o;
 #pragma unroll
     for (int e = 0; e < 4; ++e)
@@ -145,12 +155,12 @@ __device__ __forceinline__ void bstore4(__amdgpu_buffer_rsrc_t r, unsigned off, 
 #pragma unroll
     for (int e = 0; e < 4; ++e)
         w[e] = __float_as_uint(v.v[e]);
-    __builtin_amdgcn_raw_buffer_store_b128(w, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, off, 0, kStream);
 }
 
 __device__ __forceinline__ void bstore1(__amdgpu_buffer_rsrc_t r, unsigned off, float v)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, kStream);
 }
 
 template <int TXV, int TY, int RY>
@@ -260,7 +270,7 @@ __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
         const __amdgpu_buffer_rsrc_t rc = plane_rsrc(a.cur, pbytes, z0 - 4 + i);
 #pragma unroll
         for (int r = 0; r < RY; ++r)
-            q[i][r] = bload4(rc, own_ld[r]);
+            q[i][r] = bload4<kKeep>(rc, own_ld[r]);
     }
 
     // values of the next plane, loaded one plane ahead into the set of the
@@ -274,13 +284,13 @@ __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
         const __amdgpu_buffer_rsrc_t rh = plane_rsrc(a.cur, pbytes, z);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            q[slot][r] = bload4(rq, own_ld[r]);
-            pv[set][r] = bload4(rp, own_in[r]);
-            kv[set][r] = bload4(rk, own_in[r]);
+            q[slot][r] = bload4<kKeep>(rq, own_ld[r]);
+            pv[set][r] = bload4<kStream>(rp, own_in[r]);
+            kv[set][r] = bload4<kStream>(rk, own_in[r]);
         }
 #pragma unroll
         for (int h = 0; h < HPT; ++h)
-            hv[set][h] = bload4(rh, h_b[h]);
+            hv[set][h] = bload4<kKeep>(rh, h_b[h]);
         gzv[set] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(gz_r, 4u * z, 0, 0));
     };
     prefetch(z0, 8, 0);
@@ -469,6 +479,10 @@ const Variant kVariants[] = {
     {"t256x8_r2", step_tiled<64, 4, 2>, 64, 4, 2},
     {"t64x16_r2", step_tiled<16, 8, 2>, 16, 8, 2},
     {"t128x32_r4", step_tiled<32, 8, 4>, 32, 8, 4},
+    {"t256x8_r1", step_tiled<64, 8, 1>, 64, 8, 1},
+    {"t64x32_r1", step_tiled<16, 32, 1>, 16, 32, 1},
+    {"t128x32_r2", step_tiled<32, 16, 2>, 32, 16, 2},
+    {"t256x16_r2", step_tiled<64, 8, 2>, 64, 8, 2},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kNaive = 1;
@@ -542,14 +556,23 @@ void sponge_profile(int n, int width, double alpha, std::vector<float> &g)
     }
 }
 
-// Choose a variant and z-chunk; fill the grid geometry.
+// Choose a variant and z-chunk; fill the grid geometry.  Measured on the
+// 512^3 workload: 128 x 16 tiles with one float4 per thread and about one
+// 512-thread work-group per CU (z split into as many chunks as that takes)
+// beat both smaller work-groups and more of them; every chunk re-reads 8
+// planes of u^n, so chunks are kept at >= 32 planes.
+constexpr int kAutoVariant = 6;     // t128x16_r1
+constexpr int kSmallVariant = 2;    // t64x16_r1 for grids of fewer than 2^22 cells
+constexpr int kTargetWorkgroups = 256;
+constexpr int kMinChunk = 32;
+
 void plan_launch(wave_ctx *c)
 {
     const int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
     int v = c->variant;
     if (v == 0) {
         const long long pts = (long long)nx * ny * nz;
-        v = pts >= (1ll << 22) ? 4 : 2;  // 128x16 tiles for large grids, 64x16 otherwise
+        v = pts >= (1ll << 22) ? kAutoVariant : kSmallVariant;
     }
     c->v_used = v;
     if (v == kNaive) {
@@ -566,11 +589,9 @@ void plan_launch(wave_ctx *c)
     const long long tiles = (long long)c->ntx * c->nty;
     int zc = c->zchunk;
     if (zc <= 0) {
-        // aim for >= 1024 work-groups (4 per CU on 256 CUs) with chunks >= 32 planes
-        long long want = (1024 + tiles - 1) / tiles;
-        zc = int((nz + want - 1) / want);
-        if (zc < 32)
-            zc = 32;
+        const long long chunks = std::max(1ll, (kTargetWorkgroups + tiles / 2) / tiles);
+        zc = int((nz + chunks - 1) / chunks);
+        zc = std::max(zc, std::min(kMinChunk, nz));
     }
     if (zc > nz)
         zc = nz;
