@@ -71,9 +71,9 @@ def cpu_baseline(p, target_seconds: float):
     kw = dict(s=p.s, src=p.src, rec=p.rec, sponge_width=p.sponge_width,
               sponge_alpha=p.sponge_alpha, nthreads=threads)
     t = time.perf_counter()
-    oracle.run(k64, p.h, 1, **kw)
-    one = time.perf_counter() - t
-    n = int(max(2, min(50, round(target_seconds / max(one, 1e-3)))))
+    oracle.run(k64, p.h, 3, **kw)
+    per_step = (time.perf_counter() - t) / 3
+    n = int(max(3, min(p.nt, round(target_seconds / max(per_step, 1e-4)))))
     t = time.perf_counter()
     oracle.run(k64, p.h, n, **kw)
     sec = time.perf_counter() - t

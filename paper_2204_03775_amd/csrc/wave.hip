@@ -557,11 +557,12 @@ void sponge_profile(int n, int width, double alpha, std::vector<float> &g)
 }
 
 // Choose a variant and z-chunk; fill the grid geometry.  Measured on the
-// 512^3 workload: 128 x 16 tiles with one float4 per thread and about one
-// 512-thread work-group per CU (z split into as many chunks as that takes)
-// beat both smaller work-groups and more of them; every chunk re-reads 8
-// planes of u^n, so chunks are kept at >= 32 planes.
-constexpr int kAutoVariant = 6;     // t128x16_r1
+// 512^3 workload: 512-thread work-groups with one float4 per thread, about
+// one per CU (z split into as many chunks as that takes), beat both smaller
+// work-groups and more of them; 256 x 8 tiles edge out 128 x 16 and 64 x 32
+// by about 1.5%.  Every chunk re-reads 8 planes of u^n, so chunks are kept
+// at >= 32 planes.
+constexpr int kAutoVariant = 10;    // t256x8_r1
 constexpr int kSmallVariant = 2;    // t64x16_r1 for grids of fewer than 2^22 cells
 constexpr int kTargetWorkgroups = 256;
 constexpr int kMinChunk = 32;

@@ -1,0 +1,134 @@
+"""Summarise rocprofv3 CSV output into short text records.
+
+  python -m paper_2204_03775_amd.profile_summary stats DIR/PREFIX --command CMD --out FILE.md
+      kernel-trace statistics (<prefix>_kernel_stats.csv): the kernels by
+      total time, with calls and average duration;
+
+  python -m paper_2204_03775_amd.profile_summary traffic \\
+      --fetch-step F --write-step W --fetch-probe PF --write-probe PW \\
+      --kernel NAME --zchunk ZC --points N --commands CMDS --out-json J --out-md M
+      HBM bytes per launch of the step kernel from FETCH_SIZE and WRITE_SIZE
+      (KiB per dispatch), each scaled by the factor that maps the same
+      counter onto the known traffic of the copy probe (8 bytes per element:
+      one read, one write).
+
+The traffic record carries the SHA-256 of the kernel source it was taken
+on; bench.py reports it only while the source is unchanged.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(_HERE, "csrc", "wave.hip")
+
+
+def _short(name: str, n: int = 90) -> str:
+    name = name.replace("(anonymous namespace)::", "")
+    return name if len(name) <= n else name[:n - 3] + "..."
+
+
+def per_kernel(counter_csv: str, counter: str):
+    """{kernel name: [value per dispatch]} for one counter."""
+    out = collections.defaultdict(list)
+    with open(counter_csv) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return out
+
+
+def pick(d, key):
+    hits = [k for k in d if key in k]
+    if len(hits) != 1:
+        raise SystemExit(f"expected one kernel matching {key!r}, found {hits}")
+    return hits[0]
+
+
+def stats(prefix: str, command: str, out: str):
+    rows = list(csv.DictReader(open(prefix + "_kernel_stats.csv")))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
+             "| kernel | calls | total ms | average us | min us | max us | % |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows[:12]:
+        lines.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                     f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def traffic(a):
+    fs = per_kernel(a.fetch_step, "FETCH_SIZE")
+    ws = per_kernel(a.write_step, "WRITE_SIZE")
+    fp = per_kernel(a.fetch_probe, "FETCH_SIZE")
+    wp = per_kernel(a.write_probe, "WRITE_SIZE")
+    ks, kp = pick(fs, "step_tiled"), pick(fp, "copy_k")
+    avg = lambda v: sum(v) / len(v)
+    copy_kib = a.probe_elements * 4 / 1024.0  # bytes read (= bytes written) by one copy
+    f_scale = copy_kib / avg(fp[kp])
+    w_scale = copy_kib / avg(wp[pick(wp, "copy_k")])
+    fetch_b = avg(fs[ks]) * f_scale * 1024
+    write_b = avg(ws[pick(ws, "step_tiled")]) * w_scale * 1024
+    algo_read, algo_write = 12 * a.points, 4 * a.points
+    rec = {
+        "kernel": a.kernel, "zchunk": a.zchunk,
+        "source_sha256": hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest(),
+        "dispatches": len(fs[ks]),
+        "fetch_kib_per_dispatch": round(avg(fs[ks]), 1),
+        "write_kib_per_dispatch": round(avg(ws[pick(ws, "step_tiled")]), 1),
+        "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+        "fetch_bytes_per_launch": round(fetch_b), "write_bytes_per_launch": round(write_b),
+        "bytes_per_launch": round(fetch_b + write_b),
+        "algorithmic_bytes_per_launch": algo_read + algo_write,
+        "read_excess": round(fetch_b / algo_read, 4), "write_excess": round(write_b / algo_write, 4),
+        "commands": a.commands,
+    }
+    json.dump(rec, open(a.out_json, "w"), indent=1)
+    lines = [
+        "# HBM traffic of the step kernel (rocprofv3 counters)", "",
+        f"Kernel `{_short(ks)}` = variant `{a.kernel}`, z-chunk {a.zchunk}, "
+        f"{a.points} interior updates per launch, {rec['dispatches']} dispatches.", "",
+        "Scale factors come from the copy probe (`copy_k`, "
+        f"{a.probe_elements} floats: {copy_kib:.0f} KiB read and written): "
+        f"FETCH_SIZE x {f_scale:.4f}, WRITE_SIZE x {w_scale:.4f}.", "",
+        "| quantity | per launch |", "|---|---:|",
+        f"| FETCH_SIZE (KiB, raw) | {rec['fetch_kib_per_dispatch']} |",
+        f"| WRITE_SIZE (KiB, raw) | {rec['write_kib_per_dispatch']} |",
+        f"| bytes read (scaled) | {fetch_b / 1e9:.4f} GB = {rec['read_excess']:.3f} x algorithmic 12 B/pt |",
+        f"| bytes written (scaled) | {write_b / 1e9:.4f} GB = {rec['write_excess']:.3f} x algorithmic 4 B/pt |",
+        f"| total | {(fetch_b + write_b) / 1e9:.4f} GB vs algorithmic {(algo_read + algo_write) / 1e9:.4f} GB |",
+        "", "Commands:", ""] + [f"    {c}" for c in a.commands]
+    open(a.out_md, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("prefix")
+    s.add_argument("--command", required=True)
+    s.add_argument("--out", required=True)
+    t = sub.add_parser("traffic")
+    for k in ("fetch-step", "write-step", "fetch-probe", "write-probe", "kernel", "out-json", "out-md"):
+        t.add_argument("--" + k, required=True)
+    t.add_argument("--zchunk", type=int, required=True)
+    t.add_argument("--points", type=int, required=True)
+    t.add_argument("--probe-elements", type=int, required=True)
+    t.add_argument("--commands", nargs="+", required=True)
+    a = ap.parse_args()
+    if a.cmd == "stats":
+        stats(a.prefix, a.command, a.out)
+    else:
+        traffic(a)
+
+
+if __name__ == "__main__":
+    main()

@@ -64,7 +64,14 @@ def test_small_parity_default_config(wave_mod, small, small_ref):
     assert e_f <= TOL and e_p <= TOL and e_t <= TOL
 
 
-@pytest.mark.parametrize("variant", list(range(1, 10)))
+N_VARIANTS = 14
+
+
+def test_variant_table_size(wave_mod):
+    assert wave_mod.wave_variant_count() == N_VARIANTS
+
+
+@pytest.mark.parametrize("variant", list(range(1, N_VARIANTS)))
 def test_small_parity_every_kernel(wave_mod, small, small_ref, variant):
     print(f"case: 64^3 x 100 steps, variant {wave_mod.wave_variant_name(variant)}", flush=True)
     cur, _, tr, _ = run_gpu(wave_mod, small, variant=variant)
