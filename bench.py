@@ -14,7 +14,12 @@ HBM before timing starts.  The JSON line on stdout carries:
              `traffic` is the HBM byte count per launch measured with
              rocprofv3 counters (profiles/), reported only while the kernel
              source matches the one profiled;
-  cpu_baseline  the FP64 CPU oracle on the first steps of the same shot.
+  cpu_baseline  the FP64 CPU oracle on the first steps of the same shot;
+  forms      the FP16 and BF16 storage forms (FP32 arithmetic) on the same
+             shot: throughput, speedup over FP32 and HBM fraction at their 8
+             algorithmic bytes per update, with the accuracy of all three
+             storage types against the FP64 oracle on a 128^3 crop of the
+             same model (500 steps).
 """
 from __future__ import annotations
 
@@ -84,6 +89,73 @@ def cpu_baseline(p, target_seconds: float):
                       f"cpu={_cpu_model()}"}
 
 
+def time_shots(prop, p, s, steps, warmup):
+    """Run warmup + steps complete shots; return (wall seconds of the timed
+    shots, average step-kernel seconds from HIP events on the stream)."""
+    import torch
+
+    stream = prop.stream
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+
+    def shot(i=None):
+        prop.reset()
+        if i is not None:
+            starts[i].record(stream)
+        prop.run(p.nt, s)
+        if i is not None:
+            ends[i].record(stream)
+
+    for _ in range(warmup):
+        shot()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        shot(i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prop.sync()
+    kernel_s = sum(a.elapsed_time(b) for a, b in zip(starts, ends)) / 1e3 / (steps * p.nt)
+    return wall, kernel_s
+
+
+def result_ok(prop) -> bool:
+    import torch
+
+    field = prop.export(0)
+    tr = prop.traces[:, :prop.nrec]
+    return bool(torch.isfinite(field).all().item() and torch.isfinite(tr).all().item()
+                and tr.abs().max().item() > 0)
+
+
+def crop_accuracy(threads):
+    """rel-L2 of the final field and traces against the FP64 oracle on the
+    128^3 crop (500 steps) for every storage type."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2204_03775_amd import inputs, wave
+
+    p = inputs.crop_shot()
+    ref = oracle.run(p.k64(), p.h, p.nt, s=p.s, src=p.src, rec=p.rec, sponge_width=p.sponge_width,
+                     sponge_alpha=p.sponge_alpha, nthreads=threads)
+    s = torch.tensor(p.s, dtype=torch.float32, device="cuda")
+    out = {}
+    for dt in ("f32", "f16", "bf16"):
+        prop = wave.Propagator(p.nx, p.ny, p.nz, p.h, p.k32(), src=p.src, rec=p.rec,
+                               sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha, dtype=dt)
+        prop.record(p.nt)
+        prop.run(p.nt, s)
+        f = prop.export(0).cpu().numpy().astype(np.float64)
+        prop.sync()
+        tr = prop.traces[:, :prop.nrec].cpu().numpy().astype(np.float64)
+        prop.close()
+        out[dt] = {"rel_l2_field": float(np.linalg.norm(f - ref[0]) / np.linalg.norm(ref[0])),
+                   "rel_l2_traces": float(np.linalg.norm(tr - ref[2]) / np.linalg.norm(ref[2]))}
+    return out
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -104,6 +176,7 @@ def main() -> int:
     ap.add_argument("--variant", default="auto", help="kernel variant name (auto = library choice)")
     ap.add_argument("--zchunk", type=int, default=0, help="z planes per work-group (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16 storage forms")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
 
@@ -133,36 +206,8 @@ def main() -> int:
     log(f"kernel {kname}, z-chunk {zchunk}, {nwg} work-groups per step")
     prop.record(p.nt)
     s = torch.tensor(p.s, dtype=torch.float32, device="cuda")
-    stream = prop.stream
-
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-
-    def shot(i=None):
-        prop.reset()
-        if i is not None:
-            starts[i].record(stream)
-        prop.run(p.nt, s)
-        if i is not None:
-            ends[i].record(stream)
-
-    for _ in range(args.warmup):
-        shot()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        shot(i)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prop.sync()
-
-    kernel_s = sum(a.elapsed_time(b) for a, b in zip(starts, ends)) / 1e3 / (args.steps * p.nt)
-    cur, _, _ = prop.fields()
-    field = prop.interior(cur)
-    tr = prop.traces[:, :prop.nrec]
-    ok = bool(torch.isfinite(field).all().item() and torch.isfinite(tr).all().item()
-              and tr.abs().max().item() > 0)
-    if not ok:
+    wall, kernel_s = time_shots(prop, p, s, args.steps, args.warmup)
+    if not result_ok(prop):
         log("error: non-finite or empty result")
         return 1
 
@@ -173,6 +218,41 @@ def main() -> int:
     log(f"{gpts:.1f} Gpts/s wall, kernel {kernel_s * 1e6:.1f} us/launch = {achieved:.0f} GB/s "
         f"({achieved / metrics.MI355X_HBM_PEAK_GBS:.3f} of peak), paper-convention "
         f"{metrics.paper_tflops(gpts):.1f} TFLOP/s")
+
+    forms = None
+    if not args.no_forms and args.workload == "large_shot":
+        prop.close()
+        forms = {}
+        for dt in ("f16", "bf16"):
+            pr = wave.Propagator(p.nx, p.ny, p.nz, p.h, p.k32(), src=p.src, rec=p.rec,
+                                 sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha, dtype=dt)
+            pr.configure(args.variant, args.zchunk)
+            v16, zc16, _ = pr.config()
+            pr.record(p.nt)
+            w16, k16 = time_shots(pr, p, s, args.steps, args.warmup)
+            if not result_ok(pr):
+                log(f"error: non-finite or empty {dt} result")
+                return 1
+            pr.close()
+            g16 = metrics.gpts_per_s(p.nx, p.ny, p.nz, p.nt * args.steps, w16)
+            a16 = metrics.BYTES_PER_POINT_16 * p.points / k16 / 1e9
+            forms[dt] = {"value": round(g16, 3), "unit": "Gpts/s", "speedup_vs_f32": round(g16 / gpts, 3),
+                         "kernel": wave.wave_variant_name(v16), "zchunk": zc16,
+                         "roofline": {"bound": "hbm", "achieved": round(a16, 1),
+                                      "peak": metrics.MI355X_HBM_PEAK_GBS, "unit": "GB/s",
+                                      "frac": round(a16 / metrics.MI355X_HBM_PEAK_GBS, 4),
+                                      "bytes_per_point": metrics.BYTES_PER_POINT_16}}
+            log(f"{dt}: {g16:.1f} Gpts/s ({g16 / gpts:.2f}x FP32), kernel {k16 * 1e6:.1f} us = "
+                f"{a16:.0f} GB/s at 8 B/pt")
+        acc = crop_accuracy(len(os.sched_getaffinity(0)))
+        for dt, a in acc.items():
+            a["workload"] = "128^3 crop of the large-shot model, own 20-cell sponge, 500 steps"
+            a["reference"] = "FP64 oracle"
+            if dt == "f32":
+                forms["f32_accuracy"] = a
+            else:
+                forms[dt]["accuracy"] = a
+            log(f"{dt} accuracy on the crop: field {a['rel_l2_field']:.3e} traces {a['rel_l2_traces']:.3e}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -203,6 +283,7 @@ def main() -> int:
                      "frac": round(achieved / metrics.MI355X_HBM_PEAK_GBS, 4),
                      "traffic": traffic},
         "cpu_baseline": cpu,
+        "forms": forms,
     }
     prop.close()
     print(json.dumps(rec), flush=True)

@@ -53,11 +53,16 @@ extern "C" {
 #define WAVE_ENOMEM (-4)    /* host or device allocation failed */
 #define WAVE_EHIP (-5)      /* a HIP runtime call or a kernel failed */
 
-/* storage types */
+/* storage types: FP32, or 16-bit with FP32 arithmetic.  A 16-bit field
+ * holds x * 2^-e with one exponent e per time level, chosen on the device
+ * each step from the previous maxima so that |x| * 2^-e < 2^14; k is kept
+ * by the library in the same format with a fixed exponent. */
 #define WAVE_F32 0
+#define WAVE_F16 1
+#define WAVE_BF16 2
 
 typedef struct wave_layout_t {
-    int64_t pitch_x;  /* elements per row (multiple of 32) */
+    int64_t pitch_x;  /* elements per row (a multiple of 128 bytes) */
     int64_t rows;     /* rows per plane = ny + 8 */
     int64_t planes;   /* planes = nz + 8 */
     int64_t x_offset; /* element offset of interior x = 0 within a row */
@@ -71,7 +76,7 @@ typedef struct wave_params_t {
     double dx, dy, dz;    /* grid spacing (> 0), same unit as V dt */
     int32_t sponge_width; /* W >= 0 cells on every face; 0 = no sponge */
     double sponge_alpha;  /* g(d) = exp(-(alpha (W - d))^2) for distance d < W */
-    int32_t dtype;        /* WAVE_F32 */
+    int32_t dtype;        /* WAVE_F32, WAVE_F16 or WAVE_BF16 */
 } wave_params_t;
 
 typedef struct wave_ctx wave_ctx;
@@ -84,10 +89,15 @@ int wave_layout(int32_t nx, int32_t ny, int32_t nz, int32_t dtype, wave_layout_t
 /*
  * Create a context on the current device.
  *   p         grid, spacing, sponge and storage type;
- *   k         device, [layout] V^2 dt^2 per cell (interior read, ghosts ignored);
- *   u_cur     device, [layout] u^n   (ghost cells zero);
- *   u_prev    device, [layout] u^{n-1} (ghost cells zero); it is overwritten
- *             by u^{n+1} in the first step (two time levels, paper Section IV-B);
+ *   k         device, V^2 dt^2 per cell as FP32 in the FP32 layout (interior
+ *             read, ghosts ignored).  With FP32 storage the library reads it
+ *             every step (keep it alive); with 16-bit storage it is read
+ *             once here and encoded into a library-owned 16-bit copy;
+ *   u_cur     device, [layout of dtype] u^n   (ghost cells zero; all zero
+ *             for 16-bit storage, whose first exponent is 0);
+ *   u_prev    device, [layout of dtype] u^{n-1} (ghost cells zero); it is
+ *             overwritten by u^{n+1} in the first step (two time levels,
+ *             paper Section IV-B);
  *   src_zyx   host, 3 interior indices of the point source, or NULL for none;
  *   rec_zyx   host, [nrec][3] interior indices of the receivers (may repeat);
  *   nrec      >= 0;
@@ -121,8 +131,13 @@ int wave_run(wave_ctx *ctx, int32_t nsteps, const float *src_dev);
  * output pointer may be NULL. */
 int wave_fields(const wave_ctx *ctx, void **cur, void **prev, int64_t *step);
 
-/* Reset the counter to 0 and the roles to those given at init (the caller
- * re-initialises the field contents). */
+/* Decode u^n (which = 0) or u^{n-1} (which = 1) into dst, an FP32 field in
+ * the FP32 layout (interior written, ghosts untouched); enqueued on the
+ * context's stream.  With FP32 storage this is a copy. */
+int wave_export(wave_ctx *ctx, int32_t which, float *dst);
+
+/* Reset the counter to 0 and the roles to those given at init, and clear
+ * the 16-bit scale history (the caller re-initialises the field contents). */
 int wave_reset(wave_ctx *ctx);
 
 /* Replace the stream used by later calls. */

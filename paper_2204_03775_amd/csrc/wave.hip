@@ -1,16 +1,16 @@
-// libwave.so: single-precision time stepping of the 3-D acoustic wave
-// equation with the 25-point, 8th-order Laplacian inside a leapfrog update
-// (paper Section III: Eq. 2, the Laplacian and Algorithm 1), written for
-// MI355X (gfx950, CDNA4, wave64).  The C ABI is declared in include/wave.h.
+// libwave.so: time stepping of the 3-D acoustic wave equation with the
+// 25-point, 8th-order Laplacian inside a leapfrog update (paper Section III:
+// Eq. 2, the Laplacian and Algorithm 1), written for MI355X (gfx950, CDNA4,
+// wave64).  The C ABI is declared in include/wave.h.
 //
 // Kernel design.  The paper maps X and Y onto its processor grid and keeps
 // the whole Z column in each processor's memory (Section IV-B); a GPU has a
 // memory hierarchy instead, so the mapping here is the usual 2.5-D one:
 //   - a work-group owns an x-y tile and a range of z planes and marches
 //     through them;
-//   - each thread owns a float4 of 4 consecutive x cells in RY rows and
-//     keeps its z column z-4 .. z+4 in a 9-deep register queue (the GPU
-//     counterpart of the paper's z update from local memory, Section IV-C);
+//   - each thread owns 4 consecutive x cells in RY rows and keeps its z
+//     column z-4 .. z+4 in a register queue (the GPU counterpart of the
+//     paper's z update from local memory, Section IV-C);
 //   - the centre plane of the tile, with a 4-cell halo in x and y, is
 //     staged in LDS (double buffered: one barrier per plane) and the x and
 //     y taps are read from there;
@@ -21,6 +21,21 @@
 //     in the same launch.
 // The step is bound by HBM bandwidth (about 3 flop per byte against a ridge
 // near 20 for FP32 vector math), so nothing here uses the matrix cores.
+//
+// Laplacian form.  With FP32 fields the Laplacian is evaluated as
+//   sum_a sum_m (c_m / h_a^2) (u(+m e_a) + u(-m e_a) - 2 u),
+// which equals the paper's form because c_0 = -2 sum c_m, and which maps a
+// constant to exactly zero whatever the rounding of the FP32 weights.  The
+// classic form c_0 u + sum c_m (...) with FP32-rounded weights does not,
+// and the small spurious mass term it leaves shifts the phase by about
+// 2e-5 over five wavelengths at 17 cells per wavelength.  16-bit storage
+// rounds each stored value far more coarsely than that, so those kernels
+// keep the classic form and its 12 fewer operations per cell.
+//
+// Storage.  Fields are FP32, or FP16 / BF16 with FP32 arithmetic: a 16-bit
+// field holds x * 2^-e for one exponent e per time level, chosen on the
+// device when the level is written so that the largest value stays below
+// 2^14 (see step_scales).  Decoding multiplies by 2^e, which is exact.
 
 #include <hip/hip_runtime.h>
 
@@ -31,6 +46,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "wave.h"
@@ -38,14 +55,20 @@
 namespace {
 
 constexpr int kGhost = 4;
-constexpr int kXOffset = 32;   // interior x = 0 at element 32 of a row: 128-byte aligned
-constexpr int kPitchAlign = 32;
+constexpr int kRowAlignBytes = 128;  // interior rows start on this boundary
 
 // 8th-order central second-derivative weights (four points each way).
 constexpr double kC0 = -205.0 / 72.0;
 constexpr double kCm[4] = {8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
-// max over wavenumbers of |c0 + 2 sum c_m cos(m kh)|, reached at kh = pi
+// max over wavenumbers of |c0 + 2 sum c_m cos(m kh)|, reached at kh = pi;
+// it also equals |c0| + 2 sum |c_m|, which bounds |lap u| by this times
+// max|u| sum 1/h^2.
 constexpr double kSymbolMax = 2048.0 / 315.0;
+
+// largest scaled magnitude a 16-bit field is written with (2^14)
+constexpr int kScaledTopExp = 14;
+
+constexpr int elem_bytes(int dtype) { return dtype == WAVE_F32 ? 4 : 2; }
 
 struct alignas(16) f4 {
     float v[4];
@@ -59,17 +82,18 @@ struct Coefs {
 };
 
 struct StepArgs {
-    const float *__restrict__ k;
-    const float *__restrict__ cur;
-    float *nxt;  // holds u^{n-1} on entry, u^{n+1} on exit (same cells, same thread)
+    const void *k;
+    const void *cur;
+    void *nxt;  // holds u^{n-1} on entry, u^{n+1} on exit (same cells, same thread)
     const float *__restrict__ gx;
     const float *__restrict__ gy;
     const float *__restrict__ gz;
     Coefs c;
     int nx, ny, nz;
     int px;             // row pitch in elements
+    int x0;             // element offset of interior x = 0 in a row
     long long plane;    // elements per plane
-    int nxq;            // ceil(nx / 4): float4 columns holding interior cells
+    int nxq;            // ceil(nx / 4): 4-cell columns holding interior cells
     int ntx, nty, nchunks, zc, nwg;
     int src_z, src_y, src_x;  // src_z < 0: no source
     const float *src_ptr;     // device value of this step, or NULL
@@ -78,17 +102,16 @@ struct StepArgs {
     const long long *rec_off; // element offset of each receiver
     const int *rec_idx;       // receiver number
     float *trace_row;         // row of this step, or NULL
+    // 16-bit storage only
+    int step;                 // n: this launch writes u^{n+1}
+    float k_scale;            // k = stored k * k_scale
+    int *exps;                // [4] exponent of u^m in slot m & 3
+    unsigned *maxes;          // [4] max |u^m| (float bits) in slot m & 3
 };
 
 __device__ __forceinline__ float src_value(const StepArgs &a)
 {
     return a.src_ptr ? a.src_ptr[0] : a.src_val;
-}
-
-// Element offset of interior (z, y, x) in the padded layout.
-__device__ __forceinline__ long long elem(const StepArgs &a, int z, int y, int x)
-{
-    return (long long)(z + kGhost) * a.plane + (long long)(y + kGhost) * a.px + kXOffset + x;
 }
 
 // Work-groups are handed to the 8 XCDs round-robin by block index; map
@@ -101,28 +124,49 @@ __device__ __forceinline__ int logical_wg()
     return (b & 7) * per + (b >> 3);
 }
 
-// Receiver epilogue: after the whole tile column is written, copy the
-// receivers this work-group owns into the trace row.
-__device__ __forceinline__ void sample_receivers(const StepArgs &a, int lid, int tid, int nt)
-{
-    if (!a.trace_row)
-        return;
-    const int r0 = a.rec_start[lid], r1 = a.rec_start[lid + 1];
-    if (r0 == r1)
-        return;
-    __syncthreads();
-    for (int i = r0 + tid; i < r1; i += nt)
-        a.trace_row[a.rec_idx[i]] = a.nxt[a.rec_off[i]];
-}
+// ---------------------------------------------------------------------------
+// storage formats
+
+template <int KIND>
+struct Store;
+template <>
+struct Store<WAVE_F32> {
+    static constexpr bool scaled = false;
+    static constexpr unsigned bytes = 4;
+};
+template <>
+struct Store<WAVE_F16> {
+    static constexpr bool scaled = true;
+    static constexpr unsigned bytes = 2;
+    static __device__ __forceinline__ float dec(unsigned bits)
+    {
+        return (float)__builtin_bit_cast(_Float16, (unsigned short)bits);
+    }
+    static __device__ __forceinline__ unsigned enc(float x)
+    {
+        return __builtin_bit_cast(unsigned short, (_Float16)x);
+    }
+};
+template <>
+struct Store<WAVE_BF16> {
+    static constexpr bool scaled = true;
+    static constexpr unsigned bytes = 2;
+    static __device__ __forceinline__ float dec(unsigned bits) { return __uint_as_float(bits << 16); }
+    static __device__ __forceinline__ unsigned enc(float x)
+    {
+        return __builtin_bit_cast(unsigned short, (__bf16)x);
+    }
+};
 
 // Raw buffer access.  A buffer resource covers one plane of one field; any
 // byte offset at or past its size reads as zero and drops stores, which is
 // how out-of-range tile cells are masked without branches.
 typedef unsigned u4raw __attribute__((vector_size(16)));
+typedef unsigned u2raw __attribute__((vector_size(8)));
 constexpr int kRsrcWord3 = 0x00020000;  // 32-bit data format, raw (stride 0) access
 constexpr unsigned kOff = 0xffffffffu;  // an offset outside every resource
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float *field, long long plane_bytes,
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *field, long long plane_bytes,
                                                             int z)
 {
     const char *p = reinterpret_cast<const char *>(field) + (long long)(z + kGhost) * plane_bytes;
@@ -138,32 +182,180 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float *field,
 constexpr int kKeep = 0;
 constexpr int kStream = 2;
 
-template <int POL>
-__device__ __forceinline__ f4 bload4(__amdgpu_buffer_rsrc_t r, unsigned off)
+// Four consecutive cells, decoded to FP32 (times `scale` for 16-bit data).
+template <int KIND, int POL>
+__device__ __forceinline__ f4 load4(__amdgpu_buffer_rsrc_t r, unsigned off, float scale)
 {
-    const u4raw v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, POL);
     f4 o;
+    if constexpr (KIND == WAVE_F32) {
+        const u4raw v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, POL);
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-        o.v[e] = __uint_as_float(v[e]);
+        for (int e = 0; e < 4; ++e)
+            o.v[e] = __uint_as_float(v[e]);
+    } else {
+        const u2raw v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, POL);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            o.v[e] = Store<KIND>::dec((v[e >> 1] >> (16 * (e & 1))) & 0xffffu) * scale;
+    }
     return o;
 }
 
-__device__ __forceinline__ void bstore4(__amdgpu_buffer_rsrc_t r, unsigned off, const f4 &v)
+template <int KIND>
+__device__ __forceinline__ void store4(__amdgpu_buffer_rsrc_t r, unsigned off, const f4 &v, float inv)
 {
-    u4raw w;
+    if constexpr (KIND == WAVE_F32) {
+        u4raw w;
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-        w[e] = __float_as_uint(v.v[e]);
-    __builtin_amdgcn_raw_buffer_store_b128(w, r, off, 0, kStream);
+        for (int e = 0; e < 4; ++e)
+            w[e] = __float_as_uint(v.v[e]);
+        __builtin_amdgcn_raw_buffer_store_b128(w, r, off, 0, kStream);
+    } else {
+        u2raw w;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            w[h] = Store<KIND>::enc(v.v[2 * h] * inv) | (Store<KIND>::enc(v.v[2 * h + 1] * inv) << 16);
+        __builtin_amdgcn_raw_buffer_store_b64(w, r, off, 0, kStream);
+    }
 }
 
-__device__ __forceinline__ void bstore1(__amdgpu_buffer_rsrc_t r, unsigned off, float v)
+template <int KIND>
+__device__ __forceinline__ void store1(__amdgpu_buffer_rsrc_t r, unsigned off, float v, float inv)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, kStream);
+    if constexpr (KIND == WAVE_F32)
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, kStream);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)Store<KIND>::enc(v * inv), r, off, 0,
+                                              kStream);
 }
 
-template <int TXV, int TY, int RY>
+// Element read outside the hot loop (receivers, exports).
+template <int KIND>
+__device__ __forceinline__ float read_elem(const void *f, long long i, float scale)
+{
+    if constexpr (KIND == WAVE_F32)
+        return static_cast<const float *>(f)[i];
+    else
+        return Store<KIND>::dec(static_cast<const unsigned short *>(f)[i]) * scale;
+}
+
+// Scales of one step with 16-bit storage.  u^{n+1} is bounded by
+// 7 max(|u^n|, |u^{n-1}|) + |s_n| (2 + 1 from the time levels, 4 from
+// k |lap| under the stability limit, G <= 1); its exponent is chosen so
+// that 8 M + |s_n| < 2^(e + 14), which leaves a factor 4 below the FP16
+// maximum.  All work-groups compute the same value from the same inputs.
+struct Scales {
+    float cur, prev, out_inv, out;
+    int e_out;
+};
+
+// The same step in the stored (scaled) units.  With U, P, K the decoded
+// but unscaled u^n, u^{n-1}, k and every scale a power of two, the stored
+// u^{n+1} is
+//   O = g (fma(K, LAP_C(U), 2A U) - g B P),
+//   A = sc_cur / sc_out, B = sc_prev / sc_out, C = k_scale * A,
+// with LAP_C the Laplacian whose weights are multiplied by C.  Scaling by
+// a power of two commutes with every FP32 rounding, so this is bit for bit
+// the decode -> compute -> encode sequence, without the per-value
+// multiplies.
+struct Folded {
+    Coefs c;       // weights times C
+    float two_a;   // 2 A
+    float b;       // B
+};
+
+__device__ __forceinline__ Folded fold_scales(const Coefs &c, const Scales &sc, float k_scale)
+{
+    Folded f;
+    const float A = sc.cur * sc.out_inv;
+    const float C = k_scale * A;
+    f.c.ctr = c.ctr * C;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        f.c.cx[m] = c.cx[m] * C;
+        f.c.cy[m] = c.cy[m] * C;
+        f.c.cz[m] = c.cz[m] * C;
+    }
+    f.two_a = 2.f * A;
+    f.b = sc.prev * sc.out_inv;
+    return f;
+}
+
+__device__ __forceinline__ Scales step_scales(const StepArgs &a)
+{
+    const int n = a.step;
+    const float m = fmaxf(__uint_as_float(a.maxes[n & 3]), __uint_as_float(a.maxes[(n + 3) & 3]));
+    const float s = a.src_z >= 0 ? fabsf(src_value(a)) : 0.f;
+    const float bound = 8.f * m + s;
+    int e = 0;
+    if (bound > 0.f && bound < INFINITY) {
+        int ex;
+        (void)frexpf(bound, &ex);  // bound < 2^ex
+        e = min(max(ex - kScaledTopExp, -110), 110);
+    }
+    Scales sc;
+    sc.cur = ldexpf(1.f, a.exps[n & 3]);
+    sc.prev = ldexpf(1.f, a.exps[(n + 3) & 3]);
+    sc.out = ldexpf(1.f, e);
+    sc.out_inv = ldexpf(1.f, -e);
+    sc.e_out = e;
+    return sc;
+}
+
+// Publish this step's exponent and clear the max slot the next step fills
+// after this one (slot n + 2, which no launch of this step reads).
+__device__ __forceinline__ void publish_scale(const StepArgs &a, const Scales &sc, int lid, int tid)
+{
+    if (lid == 0 && tid == 0) {
+        a.exps[(a.step + 1) & 3] = sc.e_out;
+        a.maxes[(a.step + 2) & 3] = 0u;
+    }
+}
+
+// Fold a per-thread max |u^{n+1}| into the step's slot: a reduction across
+// the wave, then one atomic per wave (on the float bit pattern, valid for
+// non-negative values).
+__device__ __forceinline__ void fold_max(const StepArgs &a, float m)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1)
+        m = fmaxf(m, __shfl_xor(m, d));
+    if ((threadIdx.x & 63) == 0)
+        atomicMax(&a.maxes[(a.step + 1) & 3], __float_as_uint(m));
+}
+
+// Receiver epilogue: after the whole tile column is written, copy the
+// receivers this work-group owns into the trace row.
+template <int KIND>
+__device__ __forceinline__ void sample_receivers(const StepArgs &a, int lid, int tid, int nt,
+                                                 float scale)
+{
+    if (!a.trace_row)
+        return;
+    const int r0 = a.rec_start[lid], r1 = a.rec_start[lid + 1];
+    if (r0 == r1)
+        return;
+    __syncthreads();
+    for (int i = r0 + tid; i < r1; i += nt)
+        a.trace_row[a.rec_idx[i]] = read_elem<KIND>(a.nxt, a.rec_off[i], scale);
+}
+
+// Calls f(integral_constant<int, S>) for S = B, B+1, ... < E while f
+// returns true: a loop unrolled at compile time, so every index that
+// depends on S is a constant and register arrays stay in registers.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for_while(F &&f)
+{
+    if constexpr (B < E) {
+        if (f(std::integral_constant<int, B>{}))
+            static_for_while<B + 1, E>(f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the step
+
+template <int KIND, int TXV, int TY, int RY>
 __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
 {
     constexpr int NT = TXV * TY;
@@ -173,6 +365,8 @@ __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
     constexpr int NH = 8 * TXV + 2 * TYR;    // halo float4 per plane
     constexpr int HPT = (NH + NT - 1) / NT;  // halo float4 per thread
     constexpr int QS = 10;                   // queue slots: 9 live planes + 1 being filled
+    constexpr unsigned EB = Store<KIND>::bytes;
+    constexpr bool SCALED = Store<KIND>::scaled;
     __shared__ f4 lds[2][LH][LW];
 
     const int lid = logical_wg();
@@ -188,12 +382,20 @@ __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
     const int tid = threadIdx.x;
     const int lx = tid % TXV;
     const int ly = tid / TXV;
-    const int xq0 = tx * TXV;          // first float4 column of the tile
+    const int xq0 = tx * TXV;          // first 4-cell column of the tile
     const int y0 = ty * TYR;           // first row of the tile
-    const int xq = xq0 + lx;           // this thread's float4 column
+    const int xq = xq0 + lx;           // this thread's 4-cell column
     const int x = 4 * xq;
 
-    // A float4 column may be read when it lies in [-1, nxq]: allocated and
+    Scales sc{1.f, 1.f, 1.f, 1.f, 0};
+    Folded fd{a.c, 2.f, 1.f};
+    if constexpr (SCALED) {
+        sc = step_scales(a);
+        publish_scale(a, sc, lid, tid);
+        fd = fold_scales(a.c, sc, a.k_scale);
+    }
+
+    // A 4-cell column may be read when it lies in [-1, nxq]: allocated and
     // either interior, ghost or (beyond nx + 3) never used by an interior cell.
     const bool col_load = xq <= a.nxq;
     const bool col_interior = x < a.nx;
@@ -207,7 +409,7 @@ __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
     for (int r = 0; r < RY; ++r) {
         row[r] = y0 + ly * RY + r;
         row_int[r] = col_interior && row[r] < a.ny;
-        const unsigned b = 4u * unsigned((row[r] + kGhost) * a.px + kXOffset + x);
+        const unsigned b = EB * unsigned((row[r] + kGhost) * a.px + a.x0 + x);
         own_ld[r] = (col_load && row[r] < a.ny + kGhost) ? b : kOff;
         own_in[r] = row_int[r] ? b : kOff;
     }
@@ -233,7 +435,7 @@ __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
         const int gy = y0 + hr;
         const int gq = xq0 + hc;
         const bool ok = use && gy >= -kGhost && gy < a.ny + kGhost && gq >= -1 && gq <= a.nxq;
-        h_b[h] = ok ? 4u * unsigned((gy + kGhost) * a.px + kXOffset + 4 * gq) : kOff;
+        h_b[h] = ok ? EB * unsigned((gy + kGhost) * a.px + a.x0 + 4 * gq) : kOff;
     }
 
     // sponge factors that do not change along z
@@ -257,9 +459,9 @@ __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
                 src_r = r;
         src_e = a.src_x & 3;
     }
-    const float sval = src_r >= 0 ? src_value(a) : 0.f;
+    const float sval = src_r >= 0 ? src_value(a) * sc.out_inv : 0.f;
 
-    const long long pbytes = a.plane * (long long)sizeof(float);
+    const long long pbytes = a.plane * (long long)EB;
     const __amdgpu_buffer_rsrc_t gz_r = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<float *>(a.gz), (short)0, a.nz * (int)sizeof(float), kRsrcWord3);
 
@@ -270,7 +472,7 @@ __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
         const __amdgpu_buffer_rsrc_t rc = plane_rsrc(a.cur, pbytes, z0 - 4 + i);
 #pragma unroll
         for (int r = 0; r < RY; ++r)
-            q[i][r] = bload4<kKeep>(rc, own_ld[r]);
+            q[i][r] = load4<KIND, kKeep>(rc, own_ld[r], 1.f);
     }
 
     // values of the next plane, loaded one plane ahead into the set of the
@@ -284,24 +486,25 @@ __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
         const __amdgpu_buffer_rsrc_t rh = plane_rsrc(a.cur, pbytes, z);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            q[slot][r] = bload4<kKeep>(rq, own_ld[r]);
-            pv[set][r] = bload4<kStream>(rp, own_in[r]);
-            kv[set][r] = bload4<kStream>(rk, own_in[r]);
+            q[slot][r] = load4<KIND, kKeep>(rq, own_ld[r], 1.f);
+            pv[set][r] = load4<KIND, kStream>(rp, own_in[r], 1.f);
+            kv[set][r] = load4<KIND, kStream>(rk, own_in[r], 1.f);
         }
 #pragma unroll
         for (int h = 0; h < HPT; ++h)
-            hv[set][h] = bload4<kKeep>(rh, h_b[h]);
+            hv[set][h] = load4<KIND, kKeep>(rh, h_b[h], 1.f);
         gzv[set] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(gz_r, 4u * z, 0, 0));
     };
     prefetch(z0, 8, 0);
 
-    const Coefs c = a.c;
+    float tmax = 0.f;  // max |stored u^{n+1}| written by this thread (16-bit storage)
+    const Coefs c = fd.c;
     for (int zb = z0; zb < z1; zb += QS) {
-#pragma unroll
-        for (int s = 0; s < QS; ++s) {
+        static_for_while<0, QS>([&](auto phase) __attribute__((always_inline)) -> bool {
+            constexpr int s = decltype(phase)::value;
             const int z = zb + s;
             if (z >= z1)
-                break;
+                return false;
             const int cur_set = s & 1;
             // next plane (clamped on the last one, whose loads go unused)
             prefetch(min(z + 1, z1 - 1), (s + 9) % QS, cur_set ^ 1);
@@ -344,18 +547,41 @@ __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
                 f4 out;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    float lap = c.ctr * ctr.v[e];
+                    float lap;
+                    if constexpr (SCALED) {
+                        lap = c.ctr * ctr.v[e];
 #pragma unroll
-                    for (int m = 1; m <= 4; ++m) {
-                        lap = fmaf(c.cx[m - 1], xs[4 + e + m] + xs[4 + e - m], lap);
-                        lap = fmaf(c.cy[m - 1], ycol[4 + r + m].v[e] + ycol[4 + r - m].v[e], lap);
-                        lap = fmaf(c.cz[m - 1],
-                                   q[(s + 4 + m) % QS][r].v[e] + q[(s + 4 - m + QS) % QS][r].v[e],
-                                   lap);
+                        for (int m = 1; m <= 4; ++m) {
+                            lap = fmaf(c.cx[m - 1], xs[4 + e + m] + xs[4 + e - m], lap);
+                            lap = fmaf(c.cy[m - 1], ycol[4 + r + m].v[e] + ycol[4 + r - m].v[e], lap);
+                            lap = fmaf(c.cz[m - 1],
+                                       q[(s + 4 + m) % QS][r].v[e] + q[(s + 4 - m + QS) % QS][r].v[e],
+                                       lap);
+                        }
+                    } else {
+                        const float u2 = 2.f * ctr.v[e];
+                        lap = 0.f;
+#pragma unroll
+                        for (int m = 1; m <= 4; ++m) {
+                            lap = fmaf(c.cx[m - 1], (xs[4 + e + m] + xs[4 + e - m]) - u2, lap);
+                            lap = fmaf(c.cy[m - 1], (ycol[4 + r + m].v[e] + ycol[4 + r - m].v[e]) - u2,
+                                       lap);
+                            lap = fmaf(c.cz[m - 1],
+                                       (q[(s + 4 + m) % QS][r].v[e] + q[(s + 4 - m + QS) % QS][r].v[e]) -
+                                           u2,
+                                       lap);
+                        }
                     }
                     const float g = gxv.v[e] * gyv[r] * gzv[cur_set];
-                    float t = fmaf(kv[cur_set][r].v[e], lap, 2.f * ctr.v[e]);
-                    t = fmaf(-g, pv[cur_set][r].v[e], t);
+                    float t, pe;
+                    if constexpr (SCALED) {
+                        t = fmaf(kv[cur_set][r].v[e], lap, fd.two_a * ctr.v[e]);
+                        pe = fd.b * pv[cur_set][r].v[e];
+                    } else {
+                        t = fmaf(kv[cur_set][r].v[e], lap, 2.f * ctr.v[e]);
+                        pe = pv[cur_set][r].v[e];
+                    }
+                    t = fmaf(-g, pe, t);
                     out.v[e] = g * t;
                 }
                 if (src_r == r && z == a.src_z) {
@@ -365,60 +591,111 @@ __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
                             out.v[e] += sval;
                 }
                 if (col_full) {
-                    bstore4(ro, own_in[r], out);
+                    store4<KIND>(ro, own_in[r], out, 1.f);
+                    if constexpr (SCALED) {
+                        if (row_int[r]) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                tmax = fmaxf(tmax, fabsf(out.v[e]));
+                        }
+                    }
                 } else if (row_int[r]) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        bstore1(ro, x + e < a.nx ? own_in[r] + 4u * e : kOff, out.v[e]);
+                    for (int e = 0; e < 4; ++e) {
+                        const bool in = x + e < a.nx;
+                        store1<KIND>(ro, in ? own_in[r] + EB * e : kOff, out.v[e], 1.f);
+                        if constexpr (SCALED)
+                            tmax = in ? fmaxf(tmax, fabsf(out.v[e])) : tmax;
+                    }
                 }
             }
-        }
+            return true;
+        });
     }
 
-    sample_receivers(a, lid, tid, NT);
+    if constexpr (SCALED)
+        fold_max(a, tmax * sc.out);
+    sample_receivers<KIND>(a, lid, tid, NT, sc.out);
 }
 
 // One thread per interior cell, every tap read from global memory: a
-// deliberately plain kernel used to cross-check the tiled one.
+// deliberately plain kernel used to cross-check the tiled one.  Same FP32
+// operations in the same order, so the two agree bit for bit.
+template <int KIND>
 __global__ __launch_bounds__(256) void step_naive(StepArgs a)
 {
+    constexpr bool SCALED = Store<KIND>::scaled;
+    Scales sc{1.f, 1.f, 1.f, 1.f, 0};
+    Folded fd{a.c, 2.f, 1.f};
+    if constexpr (SCALED) {
+        sc = step_scales(a);
+        publish_scale(a, sc, blockIdx.x, threadIdx.x);
+        fd = fold_scales(a.c, sc, a.k_scale);
+    }
+    const Coefs &c = fd.c;
     const long long n = (long long)a.nx * a.ny * a.nz;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    float amax = 0.f;
     if (i < n) {
         const int x = (int)(i % a.nx);
         const int y = (int)((i / a.nx) % a.ny);
         const int z = (int)(i / ((long long)a.nx * a.ny));
-        const long long p = elem(a, z, y, x);
-        const float u = a.cur[p];
-        float lap = a.c.ctr * u;
+        const long long p =
+            (long long)(z + kGhost) * a.plane + (long long)(y + kGhost) * a.px + a.x0 + x;
+        auto U = [&](long long q) { return read_elem<KIND>(a.cur, q, 1.f); };
+        const float u = U(p);
+        // same form and order as the tiled kernel (difference form for FP32)
+        const float u2 = SCALED ? 0.f : 2.f * u;
+        float lap = SCALED ? c.ctr * u : 0.f;
         for (int m = 1; m <= 4; ++m) {
-            lap = fmaf(a.c.cx[m - 1], a.cur[p + m] + a.cur[p - m], lap);
-            lap = fmaf(a.c.cy[m - 1], a.cur[p + (long long)m * a.px] + a.cur[p - (long long)m * a.px], lap);
-            lap = fmaf(a.c.cz[m - 1], a.cur[p + m * a.plane] + a.cur[p - m * a.plane], lap);
+            lap = fmaf(c.cx[m - 1], (U(p + m) + U(p - m)) - u2, lap);
+            lap = fmaf(c.cy[m - 1], (U(p + (long long)m * a.px) + U(p - (long long)m * a.px)) - u2, lap);
+            lap = fmaf(c.cz[m - 1], (U(p + m * a.plane) + U(p - m * a.plane)) - u2, lap);
         }
         const float g = a.gx[x] * a.gy[y] * a.gz[z];
-        float t = fmaf(a.k[p], lap, 2.f * u);
-        t = fmaf(-g, a.nxt[p], t);
+        const float kk = read_elem<KIND>(a.k, p, 1.f);
+        const float pp = read_elem<KIND>(a.nxt, p, 1.f);
+        float t, pe;
+        if constexpr (SCALED) {
+            t = fmaf(kk, lap, fd.two_a * u);
+            pe = fd.b * pp;
+        } else {
+            t = fmaf(kk, lap, 2.f * u);
+            pe = pp;
+        }
+        t = fmaf(-g, pe, t);
         float v = g * t;
         if (z == a.src_z && y == a.src_y && x == a.src_x)
-            v += src_value(a);
-        a.nxt[p] = v;
+            v += src_value(a) * sc.out_inv;
+        if constexpr (KIND == WAVE_F32) {
+            static_cast<float *>(a.nxt)[p] = v;
+        } else {
+            static_cast<unsigned short *>(a.nxt)[p] = (unsigned short)Store<KIND>::enc(v);
+            amax = fabsf(v);
+        }
+    }
+    if constexpr (SCALED)
+        fold_max(a, amax * sc.out);
+}
+
+// Receivers for the naive kernel (separate launch: it has no tile
+// epilogue).  With 16-bit storage the scale of u^{n+1} is the one the step
+// just published.
+template <int KIND>
+__global__ void sample_naive(const void *__restrict__ f, const long long *__restrict__ off, int nrec,
+                             float *row, const int *exps, int slot)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nrec) {
+        const float scale = Store<KIND>::scaled ? ldexpf(1.f, exps[slot]) : 1.f;
+        row[r] = read_elem<KIND>(f, off[r], scale);
     }
 }
 
-// Receivers for the naive kernel (separate launch: it has no tile epilogue).
-__global__ void sample_naive(const float *__restrict__ f, const long long *__restrict__ off,
-                             int nrec, float *row)
-{
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < nrec)
-        row[r] = f[off[r]];
-}
-
-// Max, min and a non-finite flag of k over the interior, as float bit
-// patterns (valid for non-negative values; negatives raise the flag).
+// Max, min and a non-finite flag of an FP32 k over the interior, as float
+// bit patterns (valid for non-negative values; negatives raise the flag).
 __global__ __launch_bounds__(256) void k_range(const float *__restrict__ k, int nx, int ny, int nz,
-                                               int px, long long plane, unsigned *out)
+                                               int px, int x0, long long plane, unsigned *out)
 {
     __shared__ unsigned smax[256], smin[256], sbad[256];
     unsigned mx = 0u, mn = 0x7f800000u, bad = 0u;
@@ -428,7 +705,7 @@ __global__ __launch_bounds__(256) void k_range(const float *__restrict__ k, int 
         const int x = (int)(i % nx);
         const int y = (int)((i / nx) % ny);
         const int z = (int)(i / ((long long)nx * ny));
-        const float v = k[(long long)(z + kGhost) * plane + (long long)(y + kGhost) * px + kXOffset + x];
+        const float v = k[(long long)(z + kGhost) * plane + (long long)(y + kGhost) * px + x0 + x];
         if (!(v >= 0.f) || !(v < INFINITY)) {
             bad = 1u;
         } else {
@@ -457,6 +734,33 @@ __global__ __launch_bounds__(256) void k_range(const float *__restrict__ k, int 
     }
 }
 
+// Interior copy between two layouts with an exact power-of-two rescale:
+// FP32 k into 16-bit storage (init), or a field of any storage into FP32
+// (export).  `exps`/`slot` select a device exponent for the source scale.
+template <int SRC, int DST>
+__global__ __launch_bounds__(256) void convert_interior(const void *__restrict__ src, void *dst, int nx,
+                                                        int ny, int nz, int spx, int sx0,
+                                                        long long splane, int dpx, int dx0,
+                                                        long long dplane, float scale,
+                                                        const int *exps, int slot)
+{
+    const long long n = (long long)nx * ny * nz;
+    const float sc = exps ? ldexpf(1.f, exps[slot]) : scale;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx);
+        const int y = (int)((i / nx) % ny);
+        const int z = (int)(i / ((long long)nx * ny));
+        const long long si = (long long)(z + kGhost) * splane + (long long)(y + kGhost) * spx + sx0 + x;
+        const long long di = (long long)(z + kGhost) * dplane + (long long)(y + kGhost) * dpx + dx0 + x;
+        const float v = read_elem<SRC>(src, si, 1.f);
+        if constexpr (DST == WAVE_F32)
+            static_cast<float *>(dst)[di] = v * sc;
+        else
+            static_cast<unsigned short *>(dst)[di] = (unsigned short)Store<DST>::enc(v * sc);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 
@@ -464,28 +768,33 @@ typedef void (*StepKernel)(StepArgs);
 
 struct Variant {
     const char *name;
-    StepKernel fn;  // NULL for the naive kernel
+    StepKernel fn[3];  // by storage type; all NULL for "auto" and "naive"
     int txv, ty, ry;
 };
 
+#define TILED(TXV, TY, RY) \
+    {step_tiled<WAVE_F32, TXV, TY, RY>, step_tiled<WAVE_F16, TXV, TY, RY>, step_tiled<WAVE_BF16, TXV, TY, RY>}
+
 const Variant kVariants[] = {
-    {"auto", nullptr, 0, 0, 0},
-    {"naive", nullptr, 0, 0, 0},
-    {"t64x16_r1", step_tiled<16, 16, 1>, 16, 16, 1},
-    {"t128x8_r1", step_tiled<32, 8, 1>, 32, 8, 1},
-    {"t128x16_r2", step_tiled<32, 8, 2>, 32, 8, 2},
-    {"t64x32_r2", step_tiled<16, 16, 2>, 16, 16, 2},
-    {"t128x16_r1", step_tiled<32, 16, 1>, 32, 16, 1},
-    {"t256x8_r2", step_tiled<64, 4, 2>, 64, 4, 2},
-    {"t64x16_r2", step_tiled<16, 8, 2>, 16, 8, 2},
-    {"t128x32_r4", step_tiled<32, 8, 4>, 32, 8, 4},
-    {"t256x8_r1", step_tiled<64, 8, 1>, 64, 8, 1},
-    {"t64x32_r1", step_tiled<16, 32, 1>, 16, 32, 1},
-    {"t128x32_r2", step_tiled<32, 16, 2>, 32, 16, 2},
-    {"t256x16_r2", step_tiled<64, 8, 2>, 64, 8, 2},
+    {"auto", {nullptr, nullptr, nullptr}, 0, 0, 0},
+    {"naive", {nullptr, nullptr, nullptr}, 0, 0, 0},
+    {"t64x16_r1", TILED(16, 16, 1), 16, 16, 1},
+    {"t128x8_r1", TILED(32, 8, 1), 32, 8, 1},
+    {"t128x16_r2", TILED(32, 8, 2), 32, 8, 2},
+    {"t64x32_r2", TILED(16, 16, 2), 16, 16, 2},
+    {"t128x16_r1", TILED(32, 16, 1), 32, 16, 1},
+    {"t256x8_r2", TILED(64, 4, 2), 64, 4, 2},
+    {"t64x16_r2", TILED(16, 8, 2), 16, 8, 2},
+    {"t128x32_r4", TILED(32, 8, 4), 32, 8, 4},
+    {"t256x8_r1", TILED(64, 8, 1), 64, 8, 1},
+    {"t64x32_r1", TILED(16, 32, 1), 16, 32, 1},
+    {"t128x32_r2", TILED(32, 16, 2), 32, 16, 2},
+    {"t256x16_r2", TILED(64, 8, 2), 64, 8, 2},
 };
+#undef TILED
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kNaive = 1;
+const StepKernel kNaiveFn[3] = {step_naive<WAVE_F32>, step_naive<WAVE_F16>, step_naive<WAVE_BF16>};
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -493,12 +802,15 @@ int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 struct wave_ctx {
     wave_params_t p;
-    wave_layout_t lay;
+    wave_layout_t lay;    // layout of the u fields (and of the stored k)
+    wave_layout_t lay32;  // FP32 layout (the caller's k for 16-bit storage)
     int device = 0;
     hipStream_t stream = nullptr;
-    const float *k = nullptr;
-    float *buf0 = nullptr, *buf1 = nullptr;  // roles at init: cur, prev
-    float *cur = nullptr, *prev = nullptr;
+    const void *k = nullptr;  // stored k: the caller's (FP32) or k16
+    void *k16 = nullptr;      // library-owned 16-bit k
+    float k_scale = 1.f;
+    void *buf0 = nullptr, *buf1 = nullptr;  // roles at init: cur, prev
+    void *cur = nullptr, *prev = nullptr;
     int64_t step = 0;
     int src[3] = {-1, -1, -1};
     std::vector<int32_t> rec;  // [nrec][3]
@@ -512,7 +824,7 @@ struct wave_ctx {
     int *rec_start = nullptr;
     long long *rec_off = nullptr;
     int *rec_idx = nullptr;
-    int rec_start_len = 0;
+    int *ring = nullptr;  // [8]: exps[4] then maxes[4] (16-bit storage)
     // launch configuration
     int variant = 0, zchunk = 0;  // requested (0 = auto)
     int v_used = 0, zc_used = 0;
@@ -602,21 +914,26 @@ void plan_launch(wave_ctx *c)
     c->grid = int(round_up(c->nwg, 8));
 }
 
+long long elem_offset(const wave_layout_t &l, int z, int y, int x)
+{
+    return ((long long)(z + kGhost) * l.rows + (y + kGhost)) * l.pitch_x + l.x_offset + x;
+}
+
+template <class T>
+void free_dev(T *&p)
+{
+    if (p) {
+        (void)hipFree(p);
+        p = nullptr;
+    }
+}
+
 // Per-work-group receiver lists for the tiled kernels.
 int build_receiver_tables(wave_ctx *c)
 {
-    if (c->rec_start) {
-        (void)hipFree(c->rec_start);
-        c->rec_start = nullptr;
-    }
-    if (c->rec_off) {
-        (void)hipFree(c->rec_off);
-        c->rec_off = nullptr;
-    }
-    if (c->rec_idx) {
-        (void)hipFree(c->rec_idx);
-        c->rec_idx = nullptr;
-    }
+    free_dev(c->rec_start);
+    free_dev(c->rec_off);
+    free_dev(c->rec_idx);
     if (c->v_used == kNaive)
         return WAVE_OK;
     const Variant &V = kVariants[c->v_used];
@@ -633,11 +950,9 @@ int build_receiver_tables(wave_ctx *c)
     std::vector<int> fill(start.begin(), start.end() - 1), idx(std::max(c->nrec, 1));
     std::vector<long long> off(std::max(c->nrec, 1));
     for (int r = 0; r < c->nrec; ++r) {
-        const int z = c->rec[3 * r], y = c->rec[3 * r + 1], x = c->rec[3 * r + 2];
         const int slot = fill[owner[r]]++;
         idx[slot] = r;
-        off[slot] = ((long long)(z + kGhost) * c->lay.rows + (y + kGhost)) * c->lay.pitch_x +
-                    kXOffset + x;
+        off[slot] = elem_offset(c->lay, c->rec[3 * r], c->rec[3 * r + 1], c->rec[3 * r + 2]);
     }
     HIP_TRY(c, hipMalloc(&c->rec_start, sizeof(int) * start.size()));
     HIP_TRY(c, hipMalloc(&c->rec_off, sizeof(long long) * off.size()));
@@ -645,7 +960,6 @@ int build_receiver_tables(wave_ctx *c)
     HIP_TRY(c, hipMemcpy(c->rec_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->rec_off, off.data(), sizeof(long long) * off.size(), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->rec_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice));
-    c->rec_start_len = int(start.size());
     return WAVE_OK;
 }
 
@@ -663,6 +977,7 @@ int launch_step(wave_ctx *c, const float *src_ptr, float src_val)
     a.ny = c->p.ny;
     a.nz = c->p.nz;
     a.px = int(c->lay.pitch_x);
+    a.x0 = int(c->lay.x_offset);
     a.plane = c->lay.plane;
     a.nxq = (c->p.nx + 3) / 4;
     a.ntx = c->ntx;
@@ -679,22 +994,39 @@ int launch_step(wave_ctx *c, const float *src_ptr, float src_val)
     a.rec_off = c->rec_off;
     a.rec_idx = c->rec_idx;
     a.trace_row = (c->traces && c->nrec > 0) ? c->traces + (size_t)c->step * c->nrec : nullptr;
+    a.step = int(c->step & 0x3fffffff);
+    a.k_scale = c->k_scale;
+    a.exps = c->ring;
+    a.maxes = reinterpret_cast<unsigned *>(c->ring + 4);
 
+    const int kind = c->p.dtype;
     if (c->v_used == kNaive) {
-        hipLaunchKernelGGL(step_naive, dim3(c->grid), dim3(256), 0, c->stream, a);
-        if (a.trace_row)
-            hipLaunchKernelGGL(sample_naive, dim3((c->nrec + 255) / 256), dim3(256), 0, c->stream,
-                               (const float *)c->prev, (const long long *)c->rec_off_all, c->nrec,
-                               a.trace_row);
+        hipLaunchKernelGGL(kNaiveFn[kind], dim3(c->grid), dim3(256), 0, c->stream, a);
+        if (a.trace_row) {
+            const dim3 g((c->nrec + 255) / 256), b(256);
+            const int slot = (a.step + 1) & 3;
+            const void *f = c->prev;
+            const long long *off = c->rec_off_all;
+            const int *ex = c->ring;
+            if (kind == WAVE_F32)
+                hipLaunchKernelGGL(sample_naive<WAVE_F32>, g, b, 0, c->stream, f, off, c->nrec,
+                                   a.trace_row, ex, slot);
+            else if (kind == WAVE_F16)
+                hipLaunchKernelGGL(sample_naive<WAVE_F16>, g, b, 0, c->stream, f, off, c->nrec,
+                                   a.trace_row, ex, slot);
+            else
+                hipLaunchKernelGGL(sample_naive<WAVE_BF16>, g, b, 0, c->stream, f, off, c->nrec,
+                                   a.trace_row, ex, slot);
+        }
     } else {
         const Variant &V = kVariants[c->v_used];
-        hipLaunchKernelGGL(V.fn, dim3(c->grid), dim3(V.txv * V.ty), 0, c->stream, a);
+        hipLaunchKernelGGL(V.fn[kind], dim3(c->grid), dim3(V.txv * V.ty), 0, c->stream, a);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return fail(c, WAVE_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     // u^{n+1} now lives in the old u^{n-1} buffer
-    float *t = c->prev;
+    void *t = c->prev;
     c->prev = c->cur;
     c->cur = t;
     c->step += 1;
@@ -711,28 +1043,43 @@ int check_trace_room(wave_ctx *c, int64_t nsteps)
 
 void free_device(wave_ctx *c)
 {
-    float **fs[] = {&c->gx, &c->gy, &c->gz};
-    for (float **f : fs)
-        if (*f) {
-            (void)hipFree(*f);
-            *f = nullptr;
-        }
-    if (c->rec_off_all) {
-        (void)hipFree(c->rec_off_all);
-        c->rec_off_all = nullptr;
-    }
-    if (c->rec_start) {
-        (void)hipFree(c->rec_start);
-        c->rec_start = nullptr;
-    }
-    if (c->rec_off) {
-        (void)hipFree(c->rec_off);
-        c->rec_off = nullptr;
-    }
-    if (c->rec_idx) {
-        (void)hipFree(c->rec_idx);
-        c->rec_idx = nullptr;
-    }
+    free_dev(c->gx);
+    free_dev(c->gy);
+    free_dev(c->gz);
+    free_dev(c->rec_off_all);
+    free_dev(c->rec_start);
+    free_dev(c->rec_off);
+    free_dev(c->rec_idx);
+    free_dev(c->ring);
+    free_dev(c->k16);
+}
+
+int launch_convert(hipStream_t s, int src_kind, int dst_kind, const void *src, void *dst, int nx, int ny,
+                   int nz, const wave_layout_t &sl, const wave_layout_t &dl, float scale,
+                   const int *exps, int slot)
+{
+    const long long n = (long long)nx * ny * nz;
+    const dim3 g((unsigned)std::min<long long>((n + 255) / 256, 8192)), b(256);
+    const int spx = int(sl.pitch_x), sx0 = int(sl.x_offset), dpx = int(dl.pitch_x),
+              dx0 = int(dl.x_offset);
+    const long long sp = sl.plane, dp = dl.plane;
+#define CONV(S, D)                                                                                 \
+    hipLaunchKernelGGL((convert_interior<S, D>), g, b, 0, s, src, dst, nx, ny, nz, spx, sx0, sp, dpx, \
+                       dx0, dp, scale, exps, slot)
+    if (src_kind == WAVE_F32 && dst_kind == WAVE_F16)
+        CONV(WAVE_F32, WAVE_F16);
+    else if (src_kind == WAVE_F32 && dst_kind == WAVE_BF16)
+        CONV(WAVE_F32, WAVE_BF16);
+    else if (src_kind == WAVE_F16 && dst_kind == WAVE_F32)
+        CONV(WAVE_F16, WAVE_F32);
+    else if (src_kind == WAVE_BF16 && dst_kind == WAVE_F32)
+        CONV(WAVE_BF16, WAVE_F32);
+    else if (src_kind == WAVE_F32 && dst_kind == WAVE_F32)
+        CONV(WAVE_F32, WAVE_F32);
+    else
+        return WAVE_EINVAL;
+#undef CONV
+    return hipGetLastError() == hipSuccess ? WAVE_OK : WAVE_EHIP;
 }
 
 }  // namespace
@@ -741,19 +1088,24 @@ extern "C" {
 
 int wave_layout(int32_t nx, int32_t ny, int32_t nz, int32_t dtype, wave_layout_t *out)
 {
-    if (!out || nx < 1 || ny < 1 || nz < 1 || dtype != WAVE_F32)
+    if (!out || nx < 1 || ny < 1 || nz < 1)
         return WAVE_EINVAL;
+    if (dtype != WAVE_F32 && dtype != WAVE_F16 && dtype != WAVE_BF16)
+        return WAVE_EINVAL;
+    const int64_t eb = elem_bytes(dtype);
+    const int64_t align = kRowAlignBytes / eb;
     wave_layout_t l;
     const int64_t nxq = (nx + 3) / 4;
-    l.x_offset = kXOffset;
-    l.pitch_x = round_up(kXOffset + 4 * nxq + 4, kPitchAlign);
+    l.x_offset = align;
+    l.pitch_x = round_up(align + 4 * nxq + 4, align);
     l.rows = int64_t(ny) + 2 * kGhost;
     l.planes = int64_t(nz) + 2 * kGhost;
     l.plane = l.pitch_x * l.rows;
-    if (l.plane >= (int64_t(1) << 31))
+    // one plane is addressed through one buffer resource (32-bit size)
+    if (l.plane * eb >= (int64_t(1) << 31))
         return WAVE_EINVAL;
     l.elems = l.plane * l.planes;
-    l.bytes = l.elems * int64_t(sizeof(float));
+    l.bytes = l.elems * eb;
     *out = l;
     return WAVE_OK;
 }
@@ -766,12 +1118,13 @@ int wave_init(wave_ctx **out, const wave_params_t *p, const void *k, void *u_cur
     *out = nullptr;
     if (!p || !k || !u_cur || !u_prev || u_cur == u_prev || nrec < 0 || (nrec > 0 && !rec_zyx))
         return WAVE_EINVAL;
-    // float4 accesses need 16-byte aligned fields
+    // 16-byte (FP32) / 8-byte (16-bit) cell groups need aligned fields
     if ((reinterpret_cast<uintptr_t>(k) | reinterpret_cast<uintptr_t>(u_cur) |
          reinterpret_cast<uintptr_t>(u_prev)) & 15u)
         return WAVE_EINVAL;
-    wave_layout_t lay;
-    if (wave_layout(p->nx, p->ny, p->nz, p->dtype, &lay) != WAVE_OK)
+    wave_layout_t lay, lay32;
+    if (wave_layout(p->nx, p->ny, p->nz, p->dtype, &lay) != WAVE_OK ||
+        wave_layout(p->nx, p->ny, p->nz, WAVE_F32, &lay32) != WAVE_OK)
         return WAVE_EINVAL;
     if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->dz))
         return WAVE_EINVAL;
@@ -792,10 +1145,11 @@ int wave_init(wave_ctx **out, const wave_params_t *p, const void *k, void *u_cur
         return WAVE_ENOMEM;
     c->p = *p;
     c->lay = lay;
+    c->lay32 = lay32;
     c->stream = static_cast<hipStream_t>(stream);
-    c->k = static_cast<const float *>(k);
-    c->buf0 = c->cur = static_cast<float *>(u_cur);
-    c->buf1 = c->prev = static_cast<float *>(u_prev);
+    c->k = k;
+    c->buf0 = c->cur = u_cur;
+    c->buf1 = c->prev = u_prev;
     if (src_zyx)
         for (int a = 0; a < 3; ++a)
             c->src[a] = src_zyx[a];
@@ -833,26 +1187,30 @@ int wave_init(wave_ctx **out, const wave_params_t *p, const void *k, void *u_cur
     {
         std::vector<long long> off(std::max(nrec, 1));
         for (int r = 0; r < nrec; ++r)
-            off[r] = ((long long)(c->rec[3 * r] + kGhost) * lay.rows + (c->rec[3 * r + 1] + kGhost)) *
-                         lay.pitch_x + kXOffset + c->rec[3 * r + 2];
+            off[r] = elem_offset(lay, c->rec[3 * r], c->rec[3 * r + 1], c->rec[3 * r + 2]);
         if (hipMalloc(&c->rec_off_all, sizeof(long long) * off.size()) != hipSuccess)
             return bail(WAVE_ENOMEM);
         if (hipMemcpy(c->rec_off_all, off.data(), sizeof(long long) * off.size(), hipMemcpyHostToDevice) != hipSuccess)
             return bail(WAVE_EHIP);
     }
+    if (hipMalloc(&c->ring, 8 * sizeof(int)) != hipSuccess)
+        return bail(WAVE_ENOMEM);
+    if (hipMemsetAsync(c->ring, 0, 8 * sizeof(int), c->stream) != hipSuccess)
+        return bail(WAVE_EHIP);
     plan_launch(c);
     if (build_receiver_tables(c) != WAVE_OK)
         return bail(WAVE_EHIP);
 
-    // stability: max(k) * symbol_max * sum 1/h^2 <= 4
+    // stability: max(k) * symbol_max * sum 1/h^2 <= 4 (k is FP32 in the FP32 layout)
     unsigned *d = nullptr;
     unsigned init[3] = {0u, 0x7f800000u, 0u}, res[3];
     if (hipMalloc(&d, sizeof(init)) != hipSuccess)
         return bail(WAVE_ENOMEM);
     bool ok = hipMemcpyAsync(d, init, sizeof(init), hipMemcpyHostToDevice, c->stream) == hipSuccess;
     if (ok) {
-        hipLaunchKernelGGL(k_range, dim3(1024), dim3(256), 0, c->stream, c->k, p->nx, p->ny, p->nz,
-                           int(lay.pitch_x), (long long)lay.plane, d);
+        hipLaunchKernelGGL(k_range, dim3(1024), dim3(256), 0, c->stream, (const float *)k, p->nx,
+                           p->ny, p->nz, int(lay32.pitch_x), int(lay32.x_offset),
+                           (long long)lay32.plane, d);
         ok = hipGetLastError() == hipSuccess &&
              hipMemcpyAsync(res, d, sizeof(res), hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
              hipStreamSynchronize(c->stream) == hipSuccess;
@@ -866,6 +1224,26 @@ int wave_init(wave_ctx **out, const wave_params_t *p, const void *k, void *u_cur
     std::memcpy(&kmax, &res[0], sizeof(float));
     if (double(kmax) * kSymbolMax * (ih2[0] + ih2[1] + ih2[2]) > 4.0)
         return bail(WAVE_EUNSTABLE);
+
+    // 16-bit storage: the library keeps its own k, scaled by a power of two
+    // so that max(k) lands below 2^14
+    if (p->dtype != WAVE_F32) {
+        int ex = 0;
+        if (kmax > 0.f)
+            (void)std::frexp(kmax, &ex);
+        const int ek = kmax > 0.f ? ex - kScaledTopExp : 0;
+        c->k_scale = std::ldexp(1.f, ek);
+        if (hipMalloc(&c->k16, lay.bytes) != hipSuccess)
+            return bail(WAVE_ENOMEM);
+        if (hipMemsetAsync(c->k16, 0, lay.bytes, c->stream) != hipSuccess)
+            return bail(WAVE_EHIP);
+        if (launch_convert(c->stream, WAVE_F32, p->dtype, k, c->k16, p->nx, p->ny, p->nz, lay32, lay,
+                           std::ldexp(1.f, -ek), nullptr, 0) != WAVE_OK)
+            return bail(WAVE_EHIP);
+        if (hipStreamSynchronize(c->stream) != hipSuccess)
+            return bail(WAVE_EHIP);
+        c->k = c->k16;
+    }
 
     *out = c;
     return WAVE_OK;
@@ -922,6 +1300,21 @@ int wave_fields(const wave_ctx *ctx, void **cur, void **prev, int64_t *step)
     return WAVE_OK;
 }
 
+int wave_export(wave_ctx *ctx, int32_t which, float *dst)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    if ((which != 0 && which != 1) || !dst || (reinterpret_cast<uintptr_t>(dst) & 15u))
+        return fail(ctx, WAVE_EINVAL, "wave_export: which must be 0 or 1 and dst a 16-byte aligned field");
+    const void *src = which == 0 ? ctx->cur : ctx->prev;
+    const int slot = int((ctx->step + (which == 0 ? 0 : 3)) & 3);
+    const int kind = ctx->p.dtype;
+    const int rc = launch_convert(ctx->stream, kind, WAVE_F32, src, dst, ctx->p.nx, ctx->p.ny,
+                                  ctx->p.nz, ctx->lay, ctx->lay32, 1.f,
+                                  kind == WAVE_F32 ? nullptr : ctx->ring, slot);
+    return rc == WAVE_OK ? WAVE_OK : fail(ctx, rc, "export launch failed");
+}
+
 int wave_reset(wave_ctx *ctx)
 {
     if (!ctx)
@@ -929,6 +1322,7 @@ int wave_reset(wave_ctx *ctx)
     ctx->cur = ctx->buf0;
     ctx->prev = ctx->buf1;
     ctx->step = 0;
+    HIP_TRY(ctx, hipMemsetAsync(ctx->ring, 0, 8 * sizeof(int), ctx->stream));
     return WAVE_OK;
 }
 

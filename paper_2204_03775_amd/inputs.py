@@ -15,6 +15,10 @@ The paper runs on synthetic grids whose velocity model it does not state
   4500 m/s, 1000 steps, five equal layers 1500..4500 m/s times
   (1 + 0.05 p) with p Gaussian-smoothed white noise scaled to max |p| = 1,
   20-cell sponge, 12 Hz Ricker near the top, 256 receivers on a line.
+* ``crop_shot``: the 128^3 block z 0:128, y 192:320, x 192:320 of the
+  large-shot model, its own 20-cell sponge, 500 steps, source at
+  (25, 64, 64), 88 receivers at z = 22, y = 64, x = 20..107 (accuracy of
+  the reduced-precision storage forms).
 
 Random draws use ``numpy.random.default_rng(2204 + i)`` for workload i.
 """
@@ -149,12 +153,33 @@ def small_parity() -> Problem:
 def large_shot(n: int = 512, nt: int = 1000) -> Problem:
     h = (10.0, 10.0, 10.0)
     dt = cfl_dt(4500.0, 10.0, 0.8)
-    v = layered_velocity(n, n, n, [1500.0, 2250.0, 3000.0, 3750.0, 4500.0],
-                         perturb=0.05, sigma=4.0, seed=2205)
+    v = large_model(n)
     src = (25, n // 2, n // 2)
     w = ricker(12.0, nt, dt)
     rec = line_receivers(22, n // 2, 20, n - 21, 256)
     return Problem("large_shot", n, n, n, h, dt, nt, 20, 0.015, src, rec,
+                   point_source_values(w, float(v[src]), dt, h), v)
+
+
+_LARGE_MODEL = {}
+
+
+def large_model(n: int = 512) -> np.ndarray:
+    """The large-shot velocity model (cached: generating 512^3 takes seconds)."""
+    if n not in _LARGE_MODEL:
+        _LARGE_MODEL[n] = layered_velocity(n, n, n, [1500.0, 2250.0, 3000.0, 3750.0, 4500.0],
+                                           perturb=0.05, sigma=4.0, seed=2205)
+    return _LARGE_MODEL[n]
+
+
+def crop_shot(nt: int = 500) -> Problem:
+    h = (10.0, 10.0, 10.0)
+    dt = cfl_dt(4500.0, 10.0, 0.8)
+    v = np.ascontiguousarray(large_model()[0:128, 192:320, 192:320])
+    src = (25, 64, 64)
+    w = ricker(12.0, nt, dt)
+    rec = np.array([[22, 64, x] for x in range(20, 108)], dtype=np.int32)
+    return Problem("crop_shot", 128, 128, 128, h, dt, nt, 20, 0.015, src, rec,
                    point_source_values(w, float(v[src]), dt, h), v)
 
 

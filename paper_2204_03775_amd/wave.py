@@ -27,6 +27,10 @@ WAVE_ESTATE = -3
 WAVE_ENOMEM = -4
 WAVE_EHIP = -5
 WAVE_F32 = 0
+WAVE_F16 = 1
+WAVE_BF16 = 2
+DTYPES = {"f32": WAVE_F32, "f16": WAVE_F16, "bf16": WAVE_BF16}
+_TORCH_DTYPE = {WAVE_F32: torch.float32, WAVE_F16: torch.float16, WAVE_BF16: torch.bfloat16}
 
 GHOST = 4
 
@@ -63,6 +67,7 @@ def _load():
         "wave_step": ([vp, f32], ci),
         "wave_run": ([vp, i32, vp], ci),
         "wave_fields": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64)], ci),
+        "wave_export": ([vp, i32, vp], ci),
         "wave_reset": ([vp], ci),
         "wave_set_stream": ([vp, vp], ci),
         "wave_configure": ([vp, i32, i32], ci),
@@ -148,6 +153,10 @@ def wave_fields(ctx):
     return cur.value, prev.value, step.value
 
 
+def wave_export(ctx, which: int, dst_ptr: int):
+    _check(_lib.wave_export(ctx, which, dst_ptr), ctx)
+
+
 def wave_reset(ctx):
     _check(_lib.wave_reset(ctx), ctx)
 
@@ -200,38 +209,56 @@ def variants() -> dict:
 class Propagator:
     """Fields in the library's padded layout (torch tensors on the current
     device) plus a context.  ``k`` is a dense [nz][ny][nx] array (numpy or
-    torch) of V^2 dt^2, rounded to FP32 once."""
+    torch) of V^2 dt^2, rounded to FP32 once.  ``dtype`` selects the field
+    storage: "f32", or "f16" / "bf16" (16-bit storage, FP32 arithmetic)."""
 
     def __init__(self, nx, ny, nz, h, k, *, src=None, rec=None, sponge_width=0,
-                 sponge_alpha=0.0, stream=None, device=None):
+                 sponge_alpha=0.0, stream=None, device=None, dtype="f32"):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.h = tuple(float(v) for v in h)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self.layout = wave_layout(self.nx, self.ny, self.nz)
+        self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        self.layout = wave_layout(self.nx, self.ny, self.nz, self.dtype)
+        self.layout32 = wave_layout(self.nx, self.ny, self.nz, WAVE_F32)
         n = self.layout.elems
-        self.k = torch.zeros(n, dtype=torch.float32, device=self.device)
-        self.buf = [torch.zeros(n, dtype=torch.float32, device=self.device),
-                    torch.zeros(n, dtype=torch.float32, device=self.device)]
+        tdt = _TORCH_DTYPE[self.dtype]
+        # FP32 k in the FP32 layout; with 16-bit storage the library encodes
+        # its own copy at init and this one is released afterwards
+        self.k = torch.zeros(self.layout32.elems, dtype=torch.float32, device=self.device)
+        self.buf = [torch.zeros(n, dtype=tdt, device=self.device),
+                    torch.zeros(n, dtype=tdt, device=self.device)]
         self.interior(self.k).copy_(torch.as_tensor(k).to(device=self.device, dtype=torch.float32))
         self.src = tuple(int(v) for v in src) if src is not None else None
         self.rec = rec
         self.nrec = 0 if rec is None else len(rec)
         p = wave_params_t(self.nx, self.ny, self.nz, self.h[0], self.h[1], self.h[2],
-                          int(sponge_width), float(sponge_alpha), WAVE_F32)
+                          int(sponge_width), float(sponge_alpha), self.dtype)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ctx = wave_init(p, self.k.data_ptr(), self.buf[0].data_ptr(), self.buf[1].data_ptr(),
                              self.src, rec, self.stream.cuda_stream)
+        if self.dtype != WAVE_F32:
+            self.k = None
         self.traces = None
 
     # layout helpers (views, no copies)
+    def _layout_of(self, buf):
+        return self.layout32 if buf.dtype == torch.float32 else self.layout
+
     def padded(self, buf):
-        L = self.layout
+        L = self._layout_of(buf)
         return buf.view(L.planes, L.rows, L.pitch_x)
 
     def interior(self, buf):
-        L = self.layout
+        L = self._layout_of(buf)
         x0 = L.x_offset
         return self.padded(buf)[GHOST:GHOST + self.nz, GHOST:GHOST + self.ny, x0:x0 + self.nx]
+
+    def export(self, which: int = 0):
+        """u^n (which=0) or u^{n-1} (which=1) decoded to FP32, as a dense
+        [nz][ny][nx] tensor (device)."""
+        out = torch.zeros(self.layout32.elems, dtype=torch.float32, device=self.device)
+        wave_export(self.ctx, int(which), out.data_ptr())
+        return self.interior(out)
 
     def _by_ptr(self, ptr):
         for b in self.buf:

@@ -97,7 +97,7 @@ def test_full_shot_sampled(wave_mod, oracle_lib, shot, prop):
     assert np.array_equal(tr[-1], u_new[rz, ry, rx])
 
     pts = _sample_points(p, np.random.default_rng(77))
-    k32 = prop.interior(prop.k).cpu().numpy()
+    k32 = p.k32()
     ref = oracle_lib.step_points(k32, u_cur, u_prev, p.h, pts, sponge_width=p.sponge_width,
                                  sponge_alpha=p.sponge_alpha, src=p.src,
                                  src_value=float(np.float32(p.s[p.nt - 1])))
