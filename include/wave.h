@@ -159,6 +159,45 @@ int wave_config(const wave_ctx *ctx, int32_t *variant, int32_t *zchunk, int32_t 
  * any earlier launch failed. */
 int wave_sync(wave_ctx *ctx);
 
+/*
+ * Batched runs: many shots (contexts) advanced together, one launch per
+ * time step for every group of shots that share a kernel variant and
+ * storage type (a work-group finds its shot through a per-launch table).
+ * Shots may differ in size, model, source, receivers and tile choice.
+ *   ctxs       nshots distinct contexts, configured (wave_configure) before
+ *              the batch is created and not reconfigured afterwards; the
+ *              naive kernel is not batched;
+ *   stream     the stream of every batched run (the contexts' own streams
+ *              are not used by it); required when use_graph != 0, and then
+ *              it must not be the legacy default stream;
+ *   use_graph  capture a run's launches once as a HIP graph and replay it
+ *              for later runs of the same length.
+ * The batch holds pointers to the contexts: destroy it before them.
+ */
+typedef struct wave_batch wave_batch;
+int wave_batch_create(wave_batch **out, wave_ctx *const *ctxs, int32_t nshots, void *stream,
+                      int32_t use_graph);
+
+/* Enqueue nsteps steps of every shot.  All contexts must be at the same
+ * step counter (WAVE_ESTATE otherwise).  src_dev: host array of nshots
+ * device pointers (FP32, >= nsteps values each; a NULL entry injects
+ * nothing for that shot), or NULL for no source at all.  Traces, step
+ * counters and buffer roles of every context advance exactly as if each
+ * had called wave_run.  When the run's descriptors differ from the last
+ * run's (another starting step, other buffers or sources), the call first
+ * waits for the batch stream, then uploads them. */
+int wave_batch_run(wave_batch *b, int32_t nsteps, const float *const *src_dev);
+
+/* Launch groups, work-groups and interior points of one batched step. */
+int wave_batch_info(const wave_batch *b, int32_t *groups, int64_t *workgroups_per_step,
+                    int64_t *points_per_step);
+
+/* Wait for the batch stream; WAVE_EHIP if a batched launch failed. */
+int wave_batch_sync(wave_batch *b);
+
+int wave_batch_destroy(wave_batch *b);
+const char *wave_batch_last_error(const wave_batch *b);
+
 /* Free library-owned memory (host and device); caller buffers are kept.
  * NULL is accepted. */
 int wave_destroy(wave_ctx *ctx);

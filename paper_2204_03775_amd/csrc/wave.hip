@@ -355,8 +355,10 @@ __device__ __forceinline__ void static_for_while(F &&f)
 // ---------------------------------------------------------------------------
 // the step
 
+// One work-group's share of a step: the tile and z-chunk numbered `lid`
+// (tiles x fastest, then y, then chunks) of the grid described by `a`.
 template <int KIND, int TXV, int TY, int RY>
-__global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
+__device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
 {
     constexpr int NT = TXV * TY;
     constexpr int TYR = TY * RY;             // tile rows
@@ -369,9 +371,6 @@ __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
     constexpr bool SCALED = Store<KIND>::scaled;
     __shared__ f4 lds[2][LH][LW];
 
-    const int lid = logical_wg();
-    if (lid >= a.nwg)
-        return;
     const int tx = lid % a.ntx;
     const int rest = lid / a.ntx;
     const int ty = rest % a.nty;
@@ -618,6 +617,66 @@ __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
     sample_receivers<KIND>(a, lid, tid, NT, sc.out);
 }
 
+template <int KIND, int TXV, int TY, int RY>
+__global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
+{
+    const int lid = logical_wg();
+    if (lid >= a.nwg)
+        return;
+    tile_step<KIND, TXV, TY, RY>(a, lid);
+}
+
+// ---------------------------------------------------------------------------
+// many shots per launch
+
+// A shot of a batched run.  `a` holds the shot's arguments with the buffer
+// roles of the run's first step (cur = u^{n0}, nxt = u^{n0-1}); step j of
+// the run swaps them when j is odd and offsets the trace row and source.
+struct ShotDesc {
+    StepArgs a;
+    float *traces;     // trace buffer base (row n at traces + n * nrec), or NULL
+    int nrec;
+    int n0;            // step counter at the start of the run
+    const float *src;  // source values of the run's steps, or NULL (then no source)
+};
+
+// One time step of every shot in a group: work-group b of the launch runs
+// tile b - start[s] of the shot s with start[s] <= b < start[s + 1]
+// (blocks remapped per XCD as for one shot, so an XCD's blocks are
+// neighbouring tiles of mostly one shot).
+template <int KIND, int TXV, int TY, int RY>
+__global__ __launch_bounds__(TXV *TY) void step_batch(const ShotDesc *__restrict__ shots,
+                                                       const int *__restrict__ start, int nshots,
+                                                       int total, int j)
+{
+    const int lid = logical_wg();
+    if (lid >= total)
+        return;
+    int lo = 0, hi = nshots;  // find s with start[s] <= lid < start[s + 1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= lid)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const ShotDesc &d = shots[lo];
+    StepArgs a = d.a;
+    if (j & 1) {
+        const void *t = a.cur;
+        a.cur = a.nxt;
+        a.nxt = const_cast<void *>(t);
+    }
+    const int n = d.n0 + j;
+    a.step = n & 0x3fffffff;
+    a.trace_row = d.traces ? d.traces + (size_t)n * d.nrec : nullptr;
+    a.src_ptr = d.src ? d.src + j : nullptr;
+    a.src_val = 0.f;
+    if (!d.src)
+        a.src_z = -1;  // no source values given: no injection
+    tile_step<KIND, TXV, TY, RY>(a, lid - start[lo]);
+}
+
 // One thread per interior cell, every tap read from global memory: a
 // deliberately plain kernel used to cross-check the tiled one.  Same FP32
 // operations in the same order, so the two agree bit for bit.
@@ -765,19 +824,24 @@ __global__ __launch_bounds__(256) void convert_interior(const void *__restrict__
 // host side
 
 typedef void (*StepKernel)(StepArgs);
+typedef void (*BatchKernel)(const ShotDesc *, const int *, int, int, int);
 
 struct Variant {
     const char *name;
     StepKernel fn[3];  // by storage type; all NULL for "auto" and "naive"
+    BatchKernel batch[3];
     int txv, ty, ry;
 };
 
-#define TILED(TXV, TY, RY) \
-    {step_tiled<WAVE_F32, TXV, TY, RY>, step_tiled<WAVE_F16, TXV, TY, RY>, step_tiled<WAVE_BF16, TXV, TY, RY>}
+#define TILED(TXV, TY, RY)                                                                        \
+    {step_tiled<WAVE_F32, TXV, TY, RY>, step_tiled<WAVE_F16, TXV, TY, RY>,                        \
+     step_tiled<WAVE_BF16, TXV, TY, RY>},                                                         \
+    {step_batch<WAVE_F32, TXV, TY, RY>, step_batch<WAVE_F16, TXV, TY, RY>,                        \
+     step_batch<WAVE_BF16, TXV, TY, RY>}
 
 const Variant kVariants[] = {
-    {"auto", {nullptr, nullptr, nullptr}, 0, 0, 0},
-    {"naive", {nullptr, nullptr, nullptr}, 0, 0, 0},
+    {"auto", {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, 0, 0, 0},
+    {"naive", {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, 0, 0, 0},
     {"t64x16_r1", TILED(16, 16, 1), 16, 16, 1},
     {"t128x8_r1", TILED(32, 8, 1), 32, 8, 1},
     {"t128x16_r2", TILED(32, 8, 2), 32, 8, 2},
@@ -963,7 +1027,7 @@ int build_receiver_tables(wave_ctx *c)
     return WAVE_OK;
 }
 
-int launch_step(wave_ctx *c, const float *src_ptr, float src_val)
+StepArgs make_args(const wave_ctx *c)
 {
     StepArgs a;
     a.k = c->k;
@@ -988,8 +1052,8 @@ int launch_step(wave_ctx *c, const float *src_ptr, float src_val)
     a.src_z = c->src[0];
     a.src_y = c->src[1];
     a.src_x = c->src[2];
-    a.src_ptr = src_ptr;
-    a.src_val = src_val;
+    a.src_ptr = nullptr;
+    a.src_val = 0.f;
     a.rec_start = c->rec_start;
     a.rec_off = c->rec_off;
     a.rec_idx = c->rec_idx;
@@ -998,6 +1062,14 @@ int launch_step(wave_ctx *c, const float *src_ptr, float src_val)
     a.k_scale = c->k_scale;
     a.exps = c->ring;
     a.maxes = reinterpret_cast<unsigned *>(c->ring + 4);
+    return a;
+}
+
+int launch_step(wave_ctx *c, const float *src_ptr, float src_val)
+{
+    StepArgs a = make_args(c);
+    a.src_ptr = src_ptr;
+    a.src_val = src_val;
 
     const int kind = c->p.dtype;
     if (c->v_used == kNaive) {
@@ -1079,6 +1151,71 @@ int launch_convert(hipStream_t s, int src_kind, int dst_kind, const void *src, v
     else
         return WAVE_EINVAL;
 #undef CONV
+    return hipGetLastError() == hipSuccess ? WAVE_OK : WAVE_EHIP;
+}
+
+}  // namespace
+
+struct wave_batch {
+    struct Group {
+        int kind = 0, variant = 0;
+        std::vector<int> shots;       // indices into ctx
+        std::vector<int> start;       // [shots + 1] work-group prefix
+        std::vector<ShotDesc> h_desc; // last uploaded descriptors
+        ShotDesc *d_desc = nullptr;
+        int *d_start = nullptr;
+        int total = 0, grid = 0, threads = 0;
+    };
+    std::vector<wave_ctx *> ctx;
+    std::vector<int> cfg;  // (variant, zchunk, nwg) of every shot at creation
+    std::vector<Group> groups;
+    hipStream_t stream = nullptr;
+    bool use_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_steps = -1;
+    long long points = 0, workgroups = 0;
+    std::string err;
+};
+
+namespace {
+
+int bfail(wave_batch *b, int code, const char *fmt, ...)
+{
+    if (b) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        b->err = buf;
+    }
+    return code;
+}
+
+void batch_free(wave_batch *b)
+{
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    for (auto &g : b->groups) {
+        free_dev(g.d_desc);
+        free_dev(g.d_start);
+    }
+}
+
+int batch_enqueue(wave_batch *b, int nsteps)
+{
+    for (int j = 0; j < nsteps; ++j)
+        for (auto &g : b->groups) {
+            const BatchKernel k = kVariants[g.variant].batch[g.kind];
+            hipLaunchKernelGGL(k, dim3(g.grid), dim3(g.threads), 0, b->stream,
+                               (const ShotDesc *)g.d_desc, (const int *)g.d_start,
+                               int(g.shots.size()), g.total, j);
+        }
     return hipGetLastError() == hipSuccess ? WAVE_OK : WAVE_EHIP;
 }
 
@@ -1384,6 +1521,199 @@ int wave_destroy(wave_ctx *ctx)
     free_device(ctx);
     delete ctx;
     return WAVE_OK;
+}
+
+int wave_batch_create(wave_batch **out, wave_ctx *const *ctxs, int32_t nshots, void *stream,
+                      int32_t use_graph)
+{
+    if (!out)
+        return WAVE_EINVAL;
+    *out = nullptr;
+    if (!ctxs || nshots < 1 || (use_graph && !stream))
+        return WAVE_EINVAL;
+    for (int i = 0; i < nshots; ++i) {
+        if (!ctxs[i] || ctxs[i]->v_used == kNaive)
+            return WAVE_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i])
+                return WAVE_EINVAL;
+    }
+    wave_batch *b = new (std::nothrow) wave_batch();
+    if (!b)
+        return WAVE_ENOMEM;
+    b->stream = static_cast<hipStream_t>(stream);
+    b->use_graph = use_graph != 0;
+    b->ctx.assign(ctxs, ctxs + nshots);
+    for (int i = 0; i < nshots; ++i) {
+        const wave_ctx *c = ctxs[i];
+        b->cfg.insert(b->cfg.end(), {c->v_used, c->zc_used, c->nwg});
+        b->points += (long long)c->p.nx * c->p.ny * c->p.nz;
+        b->workgroups += c->nwg;
+        int gi = -1;
+        for (size_t g = 0; g < b->groups.size(); ++g)
+            if (b->groups[g].kind == c->p.dtype && b->groups[g].variant == c->v_used)
+                gi = int(g);
+        if (gi < 0) {
+            b->groups.emplace_back();
+            gi = int(b->groups.size()) - 1;
+            b->groups[gi].kind = c->p.dtype;
+            b->groups[gi].variant = c->v_used;
+            b->groups[gi].start.push_back(0);
+        }
+        auto &g = b->groups[gi];
+        g.shots.push_back(i);
+        g.start.push_back(g.start.back() + c->nwg);
+    }
+    for (auto &g : b->groups) {
+        g.total = g.start.back();
+        g.grid = int(round_up(g.total, 8));
+        g.threads = kVariants[g.variant].txv * kVariants[g.variant].ty;
+        g.h_desc.assign(g.shots.size(), ShotDesc{});
+        if (hipMalloc(&g.d_desc, sizeof(ShotDesc) * g.shots.size()) != hipSuccess ||
+            hipMalloc(&g.d_start, sizeof(int) * g.start.size()) != hipSuccess) {
+            batch_free(b);
+            delete b;
+            return WAVE_ENOMEM;
+        }
+        std::memset(g.h_desc.data(), 0, sizeof(ShotDesc) * g.h_desc.size());
+        if (hipMemcpy(g.d_start, g.start.data(), sizeof(int) * g.start.size(), hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(g.d_desc, g.h_desc.data(), sizeof(ShotDesc) * g.h_desc.size(),
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            batch_free(b);
+            delete b;
+            return WAVE_EHIP;
+        }
+    }
+    *out = b;
+    return WAVE_OK;
+}
+
+int wave_batch_run(wave_batch *b, int32_t nsteps, const float *const *src_dev)
+{
+    if (!b)
+        return WAVE_EINVAL;
+    if (nsteps < 0)
+        return bfail(b, WAVE_EINVAL, "nsteps < 0");
+    const int64_t n0 = b->ctx[0]->step;
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+        wave_ctx *c = b->ctx[i];
+        if (c->step != n0)
+            return bfail(b, WAVE_ESTATE, "shot %zu is at step %lld, shot 0 at %lld", i,
+                         (long long)c->step, (long long)n0);
+        if (c->v_used != b->cfg[3 * i] || c->zc_used != b->cfg[3 * i + 1] || c->nwg != b->cfg[3 * i + 2])
+            return bfail(b, WAVE_ESTATE, "shot %zu was reconfigured after the batch was created", i);
+        if (check_trace_room(c, nsteps) != WAVE_OK)
+            return bfail(b, WAVE_EINVAL, "shot %zu: %s", i, c->err.c_str());
+    }
+    if (n0 + nsteps > 0x3fffffff)
+        return bfail(b, WAVE_EINVAL, "step counter out of range");
+    // descriptors of this run; upload only what changed (after the work
+    // that may still read the old ones)
+    bool synced = false;
+    for (auto &g : b->groups) {
+        std::vector<ShotDesc> d(g.shots.size());
+        std::memset(d.data(), 0, sizeof(ShotDesc) * d.size());
+        for (size_t t = 0; t < g.shots.size(); ++t) {
+            const wave_ctx *c = b->ctx[g.shots[t]];
+            d[t].a = make_args(c);
+            d[t].traces = (c->traces && c->nrec > 0) ? c->traces : nullptr;
+            d[t].nrec = c->nrec;
+            d[t].n0 = int(n0);
+            d[t].src = src_dev ? src_dev[g.shots[t]] : nullptr;
+        }
+        if (std::memcmp(d.data(), g.h_desc.data(), sizeof(ShotDesc) * d.size()) != 0) {
+            if (!synced) {
+                if (hipStreamSynchronize(b->stream) != hipSuccess)
+                    return bfail(b, WAVE_EHIP, "stream synchronisation failed");
+                synced = true;
+            }
+            if (hipMemcpy(g.d_desc, d.data(), sizeof(ShotDesc) * d.size(), hipMemcpyHostToDevice) !=
+                hipSuccess)
+                return bfail(b, WAVE_EHIP, "descriptor upload failed");
+            g.h_desc = d;
+        }
+    }
+    if (nsteps > 0) {
+        if (b->use_graph) {
+            if (b->graph_steps != nsteps) {
+                if (b->exec)
+                    (void)hipGraphExecDestroy(b->exec);
+                if (b->graph)
+                    (void)hipGraphDestroy(b->graph);
+                b->exec = nullptr;
+                b->graph = nullptr;
+                b->graph_steps = -1;
+                if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                    return bfail(b, WAVE_EHIP, "graph capture could not start");
+                const int rc = batch_enqueue(b, nsteps);
+                hipGraph_t g = nullptr;
+                const hipError_t e = hipStreamEndCapture(b->stream, &g);
+                if (rc != WAVE_OK || e != hipSuccess || !g) {
+                    if (g)
+                        (void)hipGraphDestroy(g);
+                    return bfail(b, WAVE_EHIP, "graph capture failed");
+                }
+                if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+                    (void)hipGraphDestroy(g);
+                    b->exec = nullptr;
+                    return bfail(b, WAVE_EHIP, "graph instantiation failed");
+                }
+                b->graph = g;
+                b->graph_steps = nsteps;
+            }
+            if (hipGraphLaunch(b->exec, b->stream) != hipSuccess)
+                return bfail(b, WAVE_EHIP, "graph launch failed");
+        } else if (batch_enqueue(b, nsteps) != WAVE_OK) {
+            return bfail(b, WAVE_EHIP, "batched launch failed");
+        }
+    }
+    for (wave_ctx *c : b->ctx) {
+        c->step += nsteps;
+        if (nsteps & 1) {
+            void *t = c->prev;
+            c->prev = c->cur;
+            c->cur = t;
+        }
+    }
+    return WAVE_OK;
+}
+
+int wave_batch_info(const wave_batch *b, int32_t *groups, int64_t *workgroups_per_step,
+                    int64_t *points_per_step)
+{
+    if (!b)
+        return WAVE_EINVAL;
+    if (groups)
+        *groups = int32_t(b->groups.size());
+    if (workgroups_per_step)
+        *workgroups_per_step = b->workgroups;
+    if (points_per_step)
+        *points_per_step = b->points;
+    return WAVE_OK;
+}
+
+int wave_batch_sync(wave_batch *b)
+{
+    if (!b)
+        return WAVE_EINVAL;
+    if (hipStreamSynchronize(b->stream) != hipSuccess || hipGetLastError() != hipSuccess)
+        return bfail(b, WAVE_EHIP, "batched run failed");
+    return WAVE_OK;
+}
+
+int wave_batch_destroy(wave_batch *b)
+{
+    if (!b)
+        return WAVE_OK;
+    batch_free(b);
+    delete b;
+    return WAVE_OK;
+}
+
+const char *wave_batch_last_error(const wave_batch *b)
+{
+    return b ? b->err.c_str() : "";
 }
 
 const char *wave_strerror(int code)

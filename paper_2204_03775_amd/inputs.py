@@ -15,6 +15,11 @@ The paper runs on synthetic grids whose velocity model it does not state
   4500 m/s, 1000 steps, five equal layers 1500..4500 m/s times
   (1 + 0.05 p) with p Gaussian-smoothed white noise scaled to max |p| = 1,
   20-cell sponge, 12 Hz Ricker near the top, 256 receivers on a line.
+* ``batch_shots``: 32 shots (seed 2207) on uneven grids, nx, ny drawn from
+  96..320 and nz from 96..256 (multiples of 16), each with 3..6 layers of
+  sorted velocities drawn from 1500..4500 m/s, a 10..20 Hz Ricker at least
+  25 cells from every face, 20-cell sponge, 128 receivers on the z = 22
+  line; common dt (0.8 of the limit at 4500 m/s), 600 steps.
 * ``crop_shot``: the 128^3 block z 0:128, y 192:320, x 192:320 of the
   large-shot model, its own 20-cell sponge, 500 steps, source at
   (25, 64, 64), 88 receivers at z = 22, y = 64, x = 20..107 (accuracy of
@@ -181,6 +186,31 @@ def crop_shot(nt: int = 500) -> Problem:
     rec = np.array([[22, 64, x] for x in range(20, 108)], dtype=np.int32)
     return Problem("crop_shot", 128, 128, 128, h, dt, nt, 20, 0.015, src, rec,
                    point_source_values(w, float(v[src]), dt, h), v)
+
+
+def batch_shots(n: int = 32, nt: int = 600, seed: int = 2207) -> list:
+    rng = np.random.default_rng(seed)
+    h = (10.0, 10.0, 10.0)
+    dt = cfl_dt(4500.0, 10.0, 0.8)
+    W = 20
+    shots = []
+    for i in range(n):
+        nx, ny = (int(16 * round(rng.integers(96, 321) / 16)) for _ in range(2))
+        nz = int(16 * round(rng.integers(96, 257) / 16))
+        nl = int(rng.integers(3, 7))
+        vel = np.sort(rng.uniform(1500.0, 4500.0, size=nl))
+        layer = np.minimum((np.arange(nz) * nl) // nz, nl - 1)
+        v = np.empty((nz, ny, nx), dtype=np.float32)
+        v[...] = vel[layer].astype(np.float32)[:, None, None]
+        m = W + 5
+        src = tuple(int(rng.integers(m, d - m)) for d in (nz, ny, nx))
+        f = float(rng.uniform(10.0, 20.0))
+        xs = np.linspace(m, nx - 1 - m, 128).round().astype(np.int32)
+        rec = np.stack([np.full(128, 22), np.full(128, ny // 2), xs], axis=1).astype(np.int32)
+        w = ricker(f, nt, dt)
+        shots.append(Problem(f"shot{i}_{nx}x{ny}x{nz}", nx, ny, nz, h, dt, nt, W, 0.015, src, rec,
+                             point_source_values(w, float(v[src]), dt, h), v))
+    return shots
 
 
 def random_problem(nx: int, ny: int, nz: int, nt: int, *, seed: int, h=(10.0, 12.0, 8.0),

@@ -76,6 +76,12 @@ def _load():
         "wave_config": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], ci),
         "wave_sync": ([vp], ci),
         "wave_destroy": ([vp], ci),
+        "wave_batch_create": ([ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp, i32], ci),
+        "wave_batch_run": ([vp, i32, ctypes.POINTER(vp)], ci),
+        "wave_batch_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64)], ci),
+        "wave_batch_sync": ([vp], ci),
+        "wave_batch_destroy": ([vp], ci),
+        "wave_batch_last_error": ([vp], ctypes.c_char_p),
         "wave_strerror": ([ci], ctypes.c_char_p),
         "wave_last_error": ([vp], ctypes.c_char_p),
     }
@@ -200,6 +206,44 @@ def wave_last_error(ctx) -> str:
     return _lib.wave_last_error(ctx).decode()
 
 
+def _bcheck(rc: int, b=None):
+    if rc != WAVE_OK:
+        msg = _lib.wave_strerror(rc).decode()
+        if b:
+            detail = _lib.wave_batch_last_error(b).decode()
+            if detail:
+                msg = f"{msg}: {detail}"
+        raise WaveError(rc, msg)
+
+
+def wave_batch_create(ctxs, stream, use_graph: bool = True):
+    b = ctypes.c_void_p()
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value if isinstance(c, ctypes.c_void_p) else c for c in ctxs])
+    _bcheck(_lib.wave_batch_create(ctypes.byref(b), arr, len(ctxs), stream, int(bool(use_graph))))
+    return b
+
+
+def wave_batch_run(b, nsteps: int, src_ptrs=None):
+    arr = None
+    if src_ptrs is not None:
+        arr = (ctypes.c_void_p * len(src_ptrs))(*[p or None for p in src_ptrs])
+    _bcheck(_lib.wave_batch_run(b, nsteps, arr), b)
+
+
+def wave_batch_info(b):
+    g, wg, pts = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+    _bcheck(_lib.wave_batch_info(b, ctypes.byref(g), ctypes.byref(wg), ctypes.byref(pts)), b)
+    return g.value, wg.value, pts.value
+
+
+def wave_batch_sync(b):
+    _bcheck(_lib.wave_batch_sync(b), b)
+
+
+def wave_batch_destroy(b):
+    _bcheck(_lib.wave_batch_destroy(b))
+
+
 def variants() -> dict:
     return {wave_variant_name(i): i for i in range(wave_variant_count())}
 
@@ -239,6 +283,10 @@ class Propagator:
         if self.dtype != WAVE_F32:
             self.k = None
         self.traces = None
+
+    @property
+    def points(self) -> int:
+        return self.nx * self.ny * self.nz
 
     # layout helpers (views, no copies)
     def _layout_of(self, buf):
@@ -312,6 +360,54 @@ class Propagator:
         if getattr(self, "ctx", None):
             wave_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several Propagators advanced together by one launch per step (per
+    group of shots sharing a kernel), optionally replayed from a HIP graph.
+    ``stream`` must be a non-default torch stream when ``use_graph``."""
+
+    def __init__(self, props, stream=None, use_graph: bool = True):
+        self.props = list(props)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.props[0].device)
+        self.handle = wave_batch_create([p.ctx for p in self.props], self.stream.cuda_stream, use_graph)
+
+    def info(self):
+        """(launch groups, work-groups per step, interior points per step)"""
+        return wave_batch_info(self.handle)
+
+    def run(self, nsteps: int, srcs=None):
+        """``srcs``: one device FP32 tensor (or None) per shot."""
+        ptrs = None
+        if srcs is not None:
+            ptrs = []
+            for t in srcs:
+                if t is None:
+                    ptrs.append(None)
+                else:
+                    assert t.dtype == torch.float32 and t.is_cuda and t.is_contiguous()
+                    assert t.numel() >= nsteps
+                    ptrs.append(t.data_ptr())
+        # order against work on the caller's current stream both ways
+        # (field resets before, reads after)
+        cur = torch.cuda.current_stream(self.props[0].device)
+        self.stream.wait_stream(cur)
+        wave_batch_run(self.handle, int(nsteps), ptrs)
+        cur.wait_stream(self.stream)
+
+    def sync(self):
+        wave_batch_sync(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            wave_batch_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

@@ -1,0 +1,173 @@
+"""Batched multi-shot runs (one launch per step for many shots, optionally
+replayed from a HIP graph).
+
+Exact: every shot of a batch reproduces, bit for bit, the same shot run
+alone with the same kernel configuration -- fields, buffer roles and
+traces -- for mixed sizes, kernel variants (several launch groups) and
+storage types, eagerly and from a graph replayed several times with other
+work in between.  Spot checks against the FP64 oracle: rel-L2 <= 1e-5."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2204_03775_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def make_shots():
+    sizes = [(41, 37, 29), (64, 48, 40), (97, 33, 21), (30, 70, 45), (128, 16, 24), (56, 56, 56)]
+    return [inputs.random_problem(nx, ny, nz, 23, seed=100 + i, sponge_width=4, nrec=7)
+            for i, (nx, ny, nz) in enumerate(sizes)]
+
+
+CONFIGS = [("t256x8_r1", 0), ("t64x16_r1", 16), ("t128x8_r1", 7), ("t64x32_r2", 0),
+           ("t128x16_r1", 24), ("t256x8_r1", 56)]
+
+
+def build(wave, shots, dtype="f32", configs=CONFIGS):
+    props = []
+    for p, (v, zc) in zip(shots, configs):
+        pr = wave.Propagator(p.nx, p.ny, p.nz, p.h, p.k32(), src=p.src, rec=p.rec,
+                             sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha, dtype=dtype)
+        pr.configure(v, zc)
+        pr.record(p.nt)
+        props.append(pr)
+    srcs = [torch.tensor(p.s, dtype=torch.float32, device="cuda") for p in shots]
+    return props, srcs
+
+
+def snapshot(pr):
+    cur, prev, n = pr.fields()
+    view = torch.int16 if cur.element_size() == 2 else torch.int32
+    return (pr.padded(cur).view(view).cpu().numpy().copy(),
+            pr.padded(prev).view(view).cpu().numpy().copy(),
+            pr.traces.cpu().numpy().copy(), n, cur.data_ptr() == pr.buf[0].data_ptr())
+
+
+def alone(wave, shots, dtype):
+    props, srcs = build(wave, shots, dtype)
+    out = []
+    for pr, s, p in zip(props, srcs, shots):
+        pr.run(p.nt, s)
+        pr.sync()
+        out.append(snapshot(pr))
+        pr.close()
+    return out
+
+
+def same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a[:3], b[:3])) and a[3:] == b[3:]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_individual_runs(wave_mod, dtype, graph):
+    shots = make_shots()
+    ref = alone(wave_mod, shots, dtype)
+    props, srcs = build(wave_mod, shots, dtype)
+    b = wave_mod.Batch(props, use_graph=graph)
+    groups, _, pts = b.info()
+    assert groups == 5 and pts == sum(p.points for p in shots)
+    nt = shots[0].nt
+    # split the run (odd + even part) to exercise the role bookkeeping
+    b.run(9, srcs)
+    b.run(nt - 9, [s[9:] for s in srcs])
+    b.sync()
+    for i, pr in enumerate(props):
+        print(f"case: {dtype} graph={graph} shot {i} {shots[i].name}", flush=True)
+        assert same(snapshot(pr), ref[i]), i
+    b.close()
+    for pr in props:
+        pr.close()
+
+
+def test_graph_replays_match_eager(wave_mod):
+    shots = make_shots()
+    ref = alone(wave_mod, shots, "f32")
+    props, srcs = build(wave_mod, shots, "f32")
+    b = wave_mod.Batch(props, use_graph=True)
+    nt = shots[0].nt
+    for rep in range(4):
+        for pr in props:
+            pr.reset()
+        junk = torch.randn(1 << 20, device="cuda").sum().item()  # eager work in between
+        b.run(nt, srcs)
+        b.sync()
+        for i, pr in enumerate(props):
+            assert same(snapshot(pr), ref[i]), (rep, i)
+        assert np.isfinite(junk)
+    b.close()
+    for pr in props:
+        pr.close()
+
+
+def test_batch_parity_with_oracle(wave_mod, oracle_lib):
+    shots = make_shots()[:2]
+    props, srcs = build(wave_mod, shots, "f32", CONFIGS[:2])
+    b = wave_mod.Batch(props, use_graph=True)
+    b.run(shots[0].nt, srcs)
+    b.sync()
+    for p, pr in zip(shots, props):
+        ref = oracle_lib.run(p.k64(), p.h, p.nt, s=p.s, src=p.src, rec=p.rec,
+                             sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+        cur, _, _ = pr.fields()
+        got = pr.interior(cur).cpu().numpy()
+        tr = pr.traces.cpu().numpy()[:, :pr.nrec]
+        e_f = np.linalg.norm(got - ref[0]) / np.linalg.norm(ref[0])
+        e_t = np.linalg.norm(tr - ref[2]) / np.linalg.norm(ref[2])
+        print(f"{p.name}: rel-L2 field {e_f:.3e} traces {e_t:.3e}")
+        assert e_f <= 1e-5 and e_t <= 1e-5
+    b.close()
+    for pr in props:
+        pr.close()
+
+
+def test_batch_state_errors(wave_mod):
+    shots = make_shots()[:3]
+    props, srcs = build(wave_mod, shots, "f32", CONFIGS[:3])
+    b = wave_mod.Batch(props, use_graph=False)
+    props[1].step(0.0)  # out of step with the others
+    with pytest.raises(wave_mod.WaveError) as e:
+        b.run(2, srcs)
+    assert e.value.code == wave_mod.WAVE_ESTATE
+    for pr in props:
+        pr.reset()
+    props[2].configure("t128x8_r1", 5)  # reconfigured after creation
+    with pytest.raises(wave_mod.WaveError) as e:
+        b.run(2, srcs)
+    assert e.value.code == wave_mod.WAVE_ESTATE
+    props[2].configure(*CONFIGS[2])
+    with pytest.raises(wave_mod.WaveError) as e:
+        b.run(shots[0].nt + 1)  # more rows than the trace buffers hold
+    assert e.value.code == wave_mod.WAVE_EINVAL
+    b.run(2, srcs)
+    b.sync()
+    assert all(pr.fields()[2] == 2 for pr in props)
+    b.close()
+    naive = wave_mod.Propagator(8, 8, 8, (10.0, 10.0, 10.0), np.full((8, 8, 8), 1.0, np.float32))
+    naive.configure("naive", 0)
+    with pytest.raises(wave_mod.WaveError):
+        wave_mod.Batch([naive], use_graph=False)
+    naive.close()
+    for pr in props:
+        pr.close()
+
+
+def test_autotune_choice_is_applied(wave_mod, tmp_path, monkeypatch):
+    from paper_2204_03775_amd import autotune
+
+    monkeypatch.setenv("WAVE_TUNE_CACHE", str(tmp_path / "tune.json"))
+    shots = make_shots()
+    props, srcs = build(wave_mod, shots, "f32")
+    stream = torch.cuda.Stream()
+    choice = autotune.tune_batch(props, srcs, stream, nsteps=5)
+    assert set(choice) == {autotune.size_class(p.nx) for p in shots}
+    for p, pr in zip(shots, props):
+        name, parts = choice[autotune.size_class(p.nx)]
+        v, zc, _ = pr.config()
+        assert wave_mod.wave_variant_name(v) == name and zc == -(-p.nz // parts)
+    # second call is served from the cache
+    assert autotune.tune_batch(props, srcs, stream) == choice
+    for pr in props:
+        pr.close()
