@@ -640,41 +640,64 @@ struct ShotDesc {
     const float *src;  // source values of the run's steps, or NULL (then no source)
 };
 
-// One time step of every shot in a group: work-group b of the launch runs
-// tile b - start[s] of the shot s with start[s] <= b < start[s + 1]
-// (blocks remapped per XCD as for one shot, so an XCD's blocks are
-// neighbouring tiles of mostly one shot).
+// Work items of a batched step: (shot, tile and z-chunk of that shot),
+// split into 8 contiguous ranges of about equal work, one per XCD.
+struct BatchItems {
+    const int *shot;       // [items] shot (index into the group's descriptors)
+    const int *lid;        // [items] tile/chunk number within the shot
+    const int *xcd_start;  // [9] item range of each XCD
+    int *counters;         // [2][8] tickets of the current and the next step
+};
+
+// One time step of every shot in a group, as a persistent launch: the grid
+// holds as many work-groups as fit on the GPU at once; work-group b runs on
+// XCD b % 8 (blocks are dealt to the XCDs round-robin) and takes items of
+// that XCD's range by atomic ticket until the range is exhausted, so long
+// and short items balance dynamically while neighbouring tiles still share
+// an XCD's L2.  Step j draws from counter set j & 1 and clears set
+// (j + 1) & 1 for the next step (which starts only after this one ends).
 template <int KIND, int TXV, int TY, int RY>
 __global__ __launch_bounds__(TXV *TY) void step_batch(const ShotDesc *__restrict__ shots,
-                                                       const int *__restrict__ start, int nshots,
-                                                       int total, int j)
+                                                       BatchItems it, int j)
 {
-    const int lid = logical_wg();
-    if (lid >= total)
-        return;
-    int lo = 0, hi = nshots;  // find s with start[s] <= lid < start[s + 1]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (start[mid] <= lid)
-            lo = mid;
-        else
-            hi = mid;
+    __shared__ int ticket;
+    const int xcd = blockIdx.x & 7;
+    int *cnt = it.counters + 8 * (j & 1);
+    if (blockIdx.x == 0 && threadIdx.x < 8)
+        it.counters[8 * ((j + 1) & 1) + threadIdx.x] = 0;
+    const int first = it.xcd_start[xcd], last = it.xcd_start[xcd + 1];
+    for (;;) {
+        if (threadIdx.x == 0)
+            ticket = atomicAdd(&cnt[xcd], 1);
+        __syncthreads();
+        const int item = first + ticket;
+        __syncthreads();  // all threads have read the ticket (and left the LDS of the last item)
+        if (item >= last)
+            break;
+        const ShotDesc &d = shots[it.shot[item]];
+        StepArgs a = d.a;
+        if (j & 1) {
+            const void *t = a.cur;
+            a.cur = a.nxt;
+            a.nxt = const_cast<void *>(t);
+        }
+        const int n = d.n0 + j;
+        a.step = n & 0x3fffffff;
+        a.trace_row = d.traces ? d.traces + (size_t)n * d.nrec : nullptr;
+        a.src_ptr = d.src ? d.src + j : nullptr;
+        a.src_val = 0.f;
+        if (!d.src)
+            a.src_z = -1;  // no source values given: no injection
+        tile_step<KIND, TXV, TY, RY>(a, it.lid[item]);
     }
-    const ShotDesc &d = shots[lo];
-    StepArgs a = d.a;
-    if (j & 1) {
-        const void *t = a.cur;
-        a.cur = a.nxt;
-        a.nxt = const_cast<void *>(t);
-    }
-    const int n = d.n0 + j;
-    a.step = n & 0x3fffffff;
-    a.trace_row = d.traces ? d.traces + (size_t)n * d.nrec : nullptr;
-    a.src_ptr = d.src ? d.src + j : nullptr;
-    a.src_val = 0.f;
-    if (!d.src)
-        a.src_z = -1;  // no source values given: no injection
-    tile_step<KIND, TXV, TY, RY>(a, lid - start[lo]);
+}
+
+// Clears both ticket sets at the start of a batched run (a kernel rather
+// than a memset, so that it can sit in a captured graph).
+__global__ void clear_counters(int *c)
+{
+    if (threadIdx.x < 16)
+        c[threadIdx.x] = 0;
 }
 
 // One thread per interior cell, every tap read from global memory: a
@@ -824,7 +847,7 @@ __global__ __launch_bounds__(256) void convert_interior(const void *__restrict__
 // host side
 
 typedef void (*StepKernel)(StepArgs);
-typedef void (*BatchKernel)(const ShotDesc *, const int *, int, int, int);
+typedef void (*BatchKernel)(const ShotDesc *, BatchItems, int);
 
 struct Variant {
     const char *name;
@@ -1160,10 +1183,10 @@ struct wave_batch {
     struct Group {
         int kind = 0, variant = 0;
         std::vector<int> shots;       // indices into ctx
-        std::vector<int> start;       // [shots + 1] work-group prefix
         std::vector<ShotDesc> h_desc; // last uploaded descriptors
         ShotDesc *d_desc = nullptr;
-        int *d_start = nullptr;
+        int *d_items = nullptr;       // shot[items], lid[items], xcd_start[9], counters[16]
+        BatchItems items{};
         int total = 0, grid = 0, threads = 0;
     };
     std::vector<wave_ctx *> ctx;
@@ -1203,18 +1226,19 @@ void batch_free(wave_batch *b)
     b->graph = nullptr;
     for (auto &g : b->groups) {
         free_dev(g.d_desc);
-        free_dev(g.d_start);
+        free_dev(g.d_items);
     }
 }
 
 int batch_enqueue(wave_batch *b, int nsteps)
 {
+    for (auto &g : b->groups)
+        hipLaunchKernelGGL(clear_counters, dim3(1), dim3(64), 0, b->stream, g.items.counters);
     for (int j = 0; j < nsteps; ++j)
         for (auto &g : b->groups) {
             const BatchKernel k = kVariants[g.variant].batch[g.kind];
             hipLaunchKernelGGL(k, dim3(g.grid), dim3(g.threads), 0, b->stream,
-                               (const ShotDesc *)g.d_desc, (const int *)g.d_start,
-                               int(g.shots.size()), g.total, j);
+                               (const ShotDesc *)g.d_desc, g.items, j);
         }
     return hipGetLastError() == hipSuccess ? WAVE_OK : WAVE_EHIP;
 }
@@ -1558,25 +1582,73 @@ int wave_batch_create(wave_batch **out, wave_ctx *const *ctxs, int32_t nshots, v
             gi = int(b->groups.size()) - 1;
             b->groups[gi].kind = c->p.dtype;
             b->groups[gi].variant = c->v_used;
-            b->groups[gi].start.push_back(0);
         }
-        auto &g = b->groups[gi];
-        g.shots.push_back(i);
-        g.start.push_back(g.start.back() + c->nwg);
+        b->groups[gi].shots.push_back(i);
+    }
+    int device = 0, cus = 0;
+    if (hipGetDevice(&device) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+        delete b;
+        return WAVE_EHIP;
     }
     for (auto &g : b->groups) {
-        g.total = g.start.back();
-        g.grid = int(round_up(g.total, 8));
-        g.threads = kVariants[g.variant].txv * kVariants[g.variant].ty;
+        const Variant &V = kVariants[g.variant];
+        g.threads = V.txv * V.ty;
+        // items: every tile/chunk of every shot, shot by shot in spatial
+        // order; work = cells the item updates (planes x tile cells within
+        // the grid) plus the 8 planes it re-reads
+        std::vector<int> ishot, ilid;
+        std::vector<double> work;
+        for (size_t t = 0; t < g.shots.size(); ++t) {
+            const wave_ctx *c = b->ctx[g.shots[t]];
+            const int tx = 4 * V.txv, tyr = V.ty * V.ry;
+            for (int lid = 0; lid < c->nwg; ++lid) {
+                const int ix = lid % c->ntx, rest = lid / c->ntx, iy = rest % c->nty, ch = rest / c->nty;
+                const int wx = std::min(tx, c->p.nx - ix * tx), wy = std::min(tyr, c->p.ny - iy * tyr);
+                const int wz = std::min(c->zc_used, c->p.nz - ch * c->zc_used);
+                ishot.push_back(int(t));
+                ilid.push_back(lid);
+                work.push_back(double(wx) * wy * (wz + 8));
+            }
+        }
+        g.total = int(ishot.size());
+        double wsum = 0.0;
+        for (double w : work)
+            wsum += w;
+        // 8 contiguous ranges of about equal work
+        std::vector<int> xs(9, g.total);
+        xs[0] = 0;
+        double acc = 0.0;
+        int part = 1;
+        for (int i = 0; i < g.total && part < 8; ++i) {
+            acc += work[i];
+            while (part < 8 && acc >= wsum * part / 8.0)
+                xs[part++] = i + 1;
+        }
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, V.batch[g.kind], g.threads, 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        g.grid = int(round_up(std::min<long long>((long long)per_cu * cus, g.total), 8));
+        std::vector<int> blob;
+        blob.insert(blob.end(), ishot.begin(), ishot.end());
+        blob.insert(blob.end(), ilid.begin(), ilid.end());
+        blob.insert(blob.end(), xs.begin(), xs.end());
+        blob.insert(blob.end(), 16, 0);
         g.h_desc.assign(g.shots.size(), ShotDesc{});
+        std::memset(g.h_desc.data(), 0, sizeof(ShotDesc) * g.h_desc.size());
         if (hipMalloc(&g.d_desc, sizeof(ShotDesc) * g.shots.size()) != hipSuccess ||
-            hipMalloc(&g.d_start, sizeof(int) * g.start.size()) != hipSuccess) {
+            hipMalloc(&g.d_items, sizeof(int) * blob.size()) != hipSuccess) {
             batch_free(b);
             delete b;
             return WAVE_ENOMEM;
         }
-        std::memset(g.h_desc.data(), 0, sizeof(ShotDesc) * g.h_desc.size());
-        if (hipMemcpy(g.d_start, g.start.data(), sizeof(int) * g.start.size(), hipMemcpyHostToDevice) !=
+        g.items.shot = g.d_items;
+        g.items.lid = g.d_items + g.total;
+        g.items.xcd_start = g.d_items + 2 * g.total;
+        g.items.counters = g.d_items + 2 * g.total + 9;
+        if (hipMemcpy(g.d_items, blob.data(), sizeof(int) * blob.size(), hipMemcpyHostToDevice) !=
                 hipSuccess ||
             hipMemcpy(g.d_desc, g.h_desc.data(), sizeof(ShotDesc) * g.h_desc.size(),
                       hipMemcpyHostToDevice) != hipSuccess) {
