@@ -20,6 +20,10 @@ Parity status per function (what pins it lives in ``tests/test_oracle_*``):
                    definition (the sponge is a chosen published method, not
                    something the paper fixes)
   step_points      pinned against ``run`` (same update, pointwise)
+  adjoint          pinned (central finite differences of the misfit computed
+                   with ``run``, single cells inside and outside the sponge
+                   and a random direction; dot-product test of the
+                   linearised map)
 """
 from __future__ import annotations
 
@@ -70,6 +74,9 @@ def _load():
     lib.oracle_step_points.argtypes = [ci, ci, ci, cd, cd, cd, ci, cd, fp, fp, fp, ci, ci,
                                        ci, ci, cd, ci, ip, dp]
     lib.oracle_step_points.restype = ci
+    lib.oracle_adjoint.argtypes = [ci, ci, ci, cd, cd, cd, ci, cd, dp, ci, dp, ci, ci, ci, ci, ip,
+                                   dp, dp, ci]
+    lib.oracle_adjoint.restype = ci
     _lib = lib
     return lib
 
@@ -169,3 +176,26 @@ def step_points(k32, u_cur32, u_prev32, h, pts, *, sponge_width=0, sponge_alpha=
     if rc != 0:
         raise ValueError(f"oracle_step_points rejected its arguments (rc={rc})")
     return out
+
+
+def adjoint(k: np.ndarray, h, nt: int, trace_grad, *, s=None, src=(0, 0, 0), rec=None,
+            sponge_width: int = 0, sponge_alpha: float = 0.0, nthreads: int | None = None):
+    """Gradient with respect to k (dense [nz][ny][nx], FP64) of a loss whose
+    derivative with respect to the traces [nt][nrec] is ``trace_grad``."""
+    k = np.ascontiguousarray(k, dtype=np.float64)
+    nz, ny, nx = k.shape
+    dx, dy, dz = h
+    rec = np.zeros((0, 3), dtype=np.int32) if rec is None else np.ascontiguousarray(rec, dtype=np.int32).reshape(-1, 3)
+    tg = np.ascontiguousarray(trace_grad, dtype=np.float64).reshape(nt, rec.shape[0])
+    grad = np.zeros_like(k)
+    sp = None
+    if s is not None:
+        s = np.ascontiguousarray(s, dtype=np.float64)
+        sp = _dptr(s)
+    rc = _load().oracle_adjoint(nx, ny, nz, dx, dy, dz, int(sponge_width), float(sponge_alpha),
+                                _dptr(k), int(nt), sp, int(src[0]), int(src[1]), int(src[2]),
+                                rec.shape[0], _iptr(rec), _dptr(tg), _dptr(grad),
+                                nthreads or default_threads())
+    if rc != 0:
+        raise ValueError(f"oracle_adjoint rejected its arguments (rc={rc})")
+    return grad

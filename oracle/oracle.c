@@ -7,8 +7,7 @@
  * nothing else.  It shares no code, header, table or constant with the HIP
  * library: the two are written independently from the paper.
  *
- * What is computed (paper, Section III "Finite difference for seismic
- * modeling"):
+ * What is computed (paper, Section III):
  *   - Eq. 1, the constant-density acoustic wave equation
  *     (1/V^2) u_tt - lap(u) = f;
  *   - Eq. 2, its second-order leapfrog discretisation
@@ -16,8 +15,8 @@
  *   - the 25-point Laplacian: four neighbours each way along every axis plus
  *     the centre, with per-axis coefficients c_m / h_a^2.  The centre is
  *     counted once with the sum of the three axis centre coefficients, as the
- *     paper does in its Section IV-C ("Stencil computation over the X and Y
- *     dimensions": the own-cell contribution is folded in once);
+ *     paper does for the own-cell contribution in its Section IV-C (X/Y
+ *     stencil computation);
  *   - Algorithm 1, the time loop, starting from a quiescent field, with one
  *     point source added each step (Section IV-D, time integration);
  *   - a ghost layer of 4 cells on every face (Section IV-B: the local column
@@ -322,5 +321,130 @@ int oracle_step_points(int nx, int ny, int nz, double dx, double dy, double dz,
             v += src_value;
         out[i] = v;
     }
+    return 0;
+}
+
+/*
+ * Discrete adjoint of oracle_run: the gradient with respect to k of a
+ * scalar loss whose derivative with respect to the traces is trace_grad
+ * (for the misfit 0.5 sum (trace - d_obs)^2 it is the residual).  The
+ * source values are fixed inputs (not differentiated).
+ *
+ * Derivation (Lagrangian of the time loop; not in the paper, whose method
+ * is the forward recurrence only): with constraints
+ *   C_n = a^{n+1} - G (2 a^n - G a^{n-1} + K L a^n) - s_n e_src,  n = 0..N-1,
+ * and multipliers lambda^{n+1}, stationarity in a^m (m = 1..N) gives
+ *   lambda^m = R^T g_{m-1} + 2 G lambda^{m+1} + L (K G lambda^{m+1}) - G^2 lambda^{m+2},
+ *   lambda^{N+1} = lambda^{N+2} = 0,
+ * (L symmetric, G and K diagonal), and the gradient is
+ *   dJ/dk = sum_{m=1..N} lambda^m * G * (L a^{m-1}).
+ * Every forward level is kept (small grids only).
+ *   trace_grad [nt][nrec], grad_k [nz][ny][nx] (overwritten).
+ */
+int oracle_adjoint(int nx, int ny, int nz, double dx, double dy, double dz, int sponge_width,
+                   double sponge_alpha, const double *k, int nt, const double *s, int src_z,
+                   int src_y, int src_x, int nrec, const int32_t *rec_zyx,
+                   const double *trace_grad, double *grad_k, int nthreads)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || nt < 0 || !k || !grad_k || sponge_width < 0)
+        return -1;
+    if (!(dx > 0) || !(dy > 0) || !(dz > 0))
+        return -1;
+    if (s && (src_z < 0 || src_z >= nz || src_y < 0 || src_y >= ny || src_x < 0 || src_x >= nx))
+        return -1;
+    if (nrec < 0 || (nrec > 0 && (!rec_zyx || !trace_grad)))
+        return -1;
+    for (int r = 0; r < nrec; ++r) {
+        const int32_t *q = &rec_zyx[3 * r];
+        if (q[0] < 0 || q[0] >= nz || q[1] < 0 || q[1] >= ny || q[2] < 0 || q[2] >= nx)
+            return -1;
+    }
+    if (nthreads < 1)
+        nthreads = 1;
+    double c[5];
+    oracle_coefficients(c);
+    const double idx2 = 1.0 / (dx * dx), idy2 = 1.0 / (dy * dy), idz2 = 1.0 / (dz * dz);
+    const int nxp = nx + 2 * GHOST, nyp = ny + 2 * GHOST, nzp = nz + 2 * GHOST;
+    const size_t npad = (size_t)nxp * nyp * nzp;
+    const size_t nint = (size_t)nx * ny * nz;
+
+    double *gx = malloc(sizeof(double) * (size_t)nx);
+    double *gy = malloc(sizeof(double) * (size_t)ny);
+    double *gz = malloc(sizeof(double) * (size_t)nz);
+    double *levels = calloc(npad * (size_t)(nt + 2), sizeof(double)); /* a^{-1} .. a^{N} */
+    double *lam = calloc(npad * 3, sizeof(double));                  /* lambda^{m}, ^{m+1}, ^{m+2} */
+    double *w = calloc(npad, sizeof(double));
+    if (!gx || !gy || !gz || !levels || !lam || !w) {
+        free(gx); free(gy); free(gz); free(levels); free(lam); free(w);
+        return -2;
+    }
+    oracle_sponge_profile(nx, sponge_width, sponge_alpha, gx);
+    oracle_sponge_profile(ny, sponge_width, sponge_alpha, gy);
+    oracle_sponge_profile(nz, sponge_width, sponge_alpha, gz);
+#define LEVEL(n) (levels + npad * (size_t)((n) + 1))
+#define GPT(z, y, x) (gx[x] * gy[y] * gz[z])
+
+    /* forward, keeping a^0 .. a^N (a^{-1} = a^0 = 0) */
+    for (int n = 0; n < nt; ++n) {
+        const double *cur = LEVEL(n), *prev = LEVEL(n - 1);
+        double *next = LEVEL(n + 1);
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    size_t p = pidx(z, y, x, nyp, nxp);
+                    double kk = k[((size_t)z * ny + y) * nx + x];
+                    double L = lap_at(cur, z, y, x, nyp, nxp, c, idx2, idy2, idz2);
+                    double G = GPT(z, y, x);
+                    next[p] = G * (2.0 * cur[p] - G * prev[p] + kk * L);
+                }
+        if (s)
+            next[pidx(src_z, src_y, src_x, nyp, nxp)] += s[n];
+    }
+
+    /* adjoint, from m = N down to 1 */
+    for (size_t i = 0; i < nint; ++i)
+        grad_k[i] = 0.0;
+    double *l0 = lam, *l1 = lam + npad, *l2 = lam + 2 * npad; /* lambda^m, ^{m+1}, ^{m+2} */
+    for (int m = nt; m >= 1; --m) {
+        /* w = K G lambda^{m+1} */
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    size_t p = pidx(z, y, x, nyp, nxp);
+                    w[p] = k[((size_t)z * ny + y) * nx + x] * GPT(z, y, x) * l1[p];
+                }
+        const double *am1 = LEVEL(m - 1);
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    size_t p = pidx(z, y, x, nyp, nxp);
+                    double G = GPT(z, y, x);
+                    l0[p] = 2.0 * G * l1[p] + lap_at(w, z, y, x, nyp, nxp, c, idx2, idy2, idz2) -
+                            G * G * l2[p];
+                }
+        for (int r = 0; r < nrec; ++r) {
+            const int32_t *q = &rec_zyx[3 * r];
+            l0[pidx(q[0], q[1], q[2], nyp, nxp)] += trace_grad[(size_t)(m - 1) * nrec + r];
+        }
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    size_t p = pidx(z, y, x, nyp, nxp);
+                    grad_k[((size_t)z * ny + y) * nx + x] +=
+                        l0[p] * GPT(z, y, x) * lap_at(am1, z, y, x, nyp, nxp, c, idx2, idy2, idz2);
+                }
+        /* rotate: (m, m+1, m+2) -> (m-1, m, m+1) */
+        double *t = l2;
+        l2 = l1;
+        l1 = l0;
+        l0 = t;
+    }
+#undef LEVEL
+#undef GPT
+    free(gx); free(gy); free(gz); free(levels); free(lam); free(w);
     return 0;
 }

@@ -1,0 +1,85 @@
+"""Pins of the oracle's discrete adjoint (the gradient of a trace misfit
+with respect to k = V^2 dt^2).  The adjoint is derived, not taken from the
+paper; it is pinned against the oracle's own forward run by central finite
+differences, which it must match to O(eps^2) + roundoff."""
+import numpy as np
+import pytest
+
+from paper_2204_03775_amd import inputs
+
+
+@pytest.fixture(scope="module")
+def case():
+    p = inputs.random_problem(14, 12, 11, 45, seed=77, sponge_width=3, sponge_alpha=0.1, nrec=9)
+    rng = np.random.default_rng(78)
+    k = p.k64()
+    d_obs = rng.standard_normal((p.nt, len(p.rec))) * 1e-7
+    return p, k, d_obs
+
+
+def misfit(oracle_lib, p, k, d_obs):
+    _, _, tr = oracle_lib.run(k, p.h, p.nt, s=p.s, src=p.src, rec=p.rec,
+                              sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+    return 0.5 * np.sum((tr - d_obs) ** 2), tr
+
+
+def gradient(oracle_lib, p, k, tg):
+    return oracle_lib.adjoint(k, p.h, p.nt, tg, s=p.s, src=p.src, rec=p.rec,
+                              sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+
+
+def test_single_cell_finite_differences(oracle_lib, case):
+    p, k, d_obs = case
+    J0, tr = misfit(oracle_lib, p, k, d_obs)
+    g = gradient(oracle_lib, p, k, tr - d_obs)
+    cells = [tuple(p.src), tuple(p.rec[0]), (0, 0, 0), (1, 5, 6), (5, 6, 7), (10, 11, 13),
+             (p.src[0], p.src[1], max(p.src[2] - 2, 0))]
+    for c in cells:
+        eps = 1e-4 * k[c]
+        kp, km = k.copy(), k.copy()
+        kp[c] += eps
+        km[c] -= eps
+        fd = (misfit(oracle_lib, p, kp, d_obs)[0] - misfit(oracle_lib, p, km, d_obs)[0]) / (2 * eps)
+        scale = max(abs(fd), 1e-6 * np.abs(g).max())
+        assert abs(g[c] - fd) <= 1e-6 * scale, (c, g[c], fd)
+
+
+def test_random_direction_and_eps_sweep(oracle_lib, case):
+    p, k, d_obs = case
+    rng = np.random.default_rng(5)
+    d = rng.standard_normal(k.shape) * k
+    J0, tr = misfit(oracle_lib, p, k, d_obs)
+    g = gradient(oracle_lib, p, k, tr - d_obs)
+    exact = float(np.sum(g * d))
+    errs = []
+    for eps in (1e-2, 1e-3, 1e-4, 1e-5):
+        fd = (misfit(oracle_lib, p, k + eps * d, d_obs)[0] - misfit(oracle_lib, p, k - eps * d, d_obs)[0]) / (2 * eps)
+        errs.append(abs(fd - exact) / abs(exact))
+    # central differences converge quadratically (x100 per decade) until roundoff
+    for a, b in zip(errs[:3], errs[1:]):
+        assert 50 < a / b < 200, errs
+    assert errs[-1] < 1e-8
+
+
+def test_dot_product_with_arbitrary_trace_gradient(oracle_lib, case):
+    # <J dk, w> = <dk, J^T w> for the linear-in-perturbation response of the
+    # traces, with J dk taken by a central difference (exact up to O(eps^2)).
+    p, k, _ = case
+    rng = np.random.default_rng(9)
+    w = rng.standard_normal((p.nt, len(p.rec)))
+    dk = rng.standard_normal(k.shape) * k
+    eps = 1e-5
+    _, _, tp = oracle_lib.run(k + eps * dk, p.h, p.nt, s=p.s, src=p.src, rec=p.rec,
+                              sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+    _, _, tm = oracle_lib.run(k - eps * dk, p.h, p.nt, s=p.s, src=p.src, rec=p.rec,
+                              sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+    jdk = (tp - tm) / (2 * eps)
+    lhs = float(np.sum(jdk * w))
+    rhs = float(np.sum(dk * gradient(oracle_lib, p, k, w)))
+    assert abs(lhs - rhs) <= 1e-7 * abs(rhs)
+
+
+def test_zero_trace_gradient_gives_zero(oracle_lib, case):
+    p, k, _ = case
+    g = gradient(oracle_lib, p, k, np.zeros((p.nt, len(p.rec))))
+    assert np.all(g == 0)
