@@ -25,6 +25,13 @@ HBM before timing starts.  The JSON line on stdout carries:
              and aggregate Gpts/s, against the same 32 shots run one after
              another with the library's automatic configuration (their
              traces must agree bit for bit).
+  gradient   the least-squares misfit gradient with respect to k on a 256^3
+             layered model with a Gaussian anomaly (800 steps, 128
+             receivers): checkpointed forward run (every 50 steps, and with
+             every level kept), FP64 misfit, adjoint run with FP64
+             accumulation; time against one FP32 forward run of the same
+             shot, and accuracy and speed against the FP64 oracle's adjoint
+             on a 48^3 crop (300 steps).
 """
 from __future__ import annotations
 
@@ -228,6 +235,126 @@ def batched_leg(reps: int):
             "traces_bitwise_equal_to_sequential": bool(equal), "repeats": reps}
 
 
+def gradient_leg(reps: int, threads: int):
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2204_03775_amd import inputs, wave
+
+    gp = inputs.gradient_shot()
+    p, q = gp.shot, gp.observed()
+
+    def make(pp):
+        pr = wave.Propagator(pp.nx, pp.ny, pp.nz, pp.h, pp.k32(), src=pp.src, rec=pp.rec,
+                             sponge_width=pp.sponge_width, sponge_alpha=pp.sponge_alpha)
+        pr.record(pp.nt)
+        return pr
+
+    s = torch.tensor(p.s, dtype=torch.float32, device="cuda")
+    obs = make(q)
+    obs.run(q.nt, s)
+    obs.sync()
+    d_obs = obs.traces[:, :obs.nrec].clone()
+    obs.close()
+    prop = make(p)
+
+    def forward():
+        prop.reset()
+        prop.run(p.nt, s)
+
+    def gradient(every):
+        prop.reset()
+        prop.forward_checkpointed(p.nt, s, every)
+        J, res = wave.misfit(prop.traces[:, :prop.nrec].contiguous(), d_obs)
+        return J, prop.adjoint(res)
+
+    def timed(fn, *a):
+        fn(*a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn(*a)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, out
+
+    t_fwd, _ = timed(forward)
+    t_g50, (J50, g50) = timed(gradient, gp.every)
+    info50 = prop.grad_info()
+    t_all, (Jall, gall) = timed(gradient, 0)
+    info_all = prop.grad_info()
+    same = bool(torch.equal(g50, gall) and J50.item() == Jall.item())
+    gpts = p.points * p.nt / 1e9
+    log(f"gradient 256^3 x {p.nt}: forward {t_fwd * 1e3:.1f} ms; gradient every {gp.every}: "
+        f"{t_g50 * 1e3:.1f} ms ({t_g50 / t_fwd:.2f}x forward); every level kept ({info_all[1]}): "
+        f"{t_all * 1e3:.1f} ms ({t_all / t_fwd:.2f}x); equal: {same}; misfit {J50.item():.6e}")
+    finite = bool(torch.isfinite(g50).all().item() and g50.abs().max().item() > 0)
+    prop.close()
+
+    # crop: accuracy and speed against the oracle's adjoint
+    cg = inputs.gradient_crop()
+    c, co = cg.shot, cg.observed()
+    cs = torch.tensor(c.s, dtype=torch.float32, device="cuda")
+    o2 = wave.Propagator(co.nx, co.ny, co.nz, co.h, co.k32(), src=co.src, rec=co.rec,
+                         sponge_width=co.sponge_width, sponge_alpha=co.sponge_alpha)
+    o2.record(co.nt)
+    o2.run(co.nt, cs)
+    cp = wave.Propagator(c.nx, c.ny, c.nz, c.h, c.k32(), src=c.src, rec=c.rec,
+                         sponge_width=c.sponge_width, sponge_alpha=c.sponge_alpha)
+    cp.record(c.nt)
+    d2 = None
+
+    def crop_gradient():
+        cp.reset()
+        cp.forward_checkpointed(c.nt, cs, cg.every)
+        J, res = wave.misfit(cp.traces[:, :cp.nrec].contiguous(), d2)
+        return J, cp.adjoint(res)
+
+    o2.sync()
+    d2 = o2.traces[:, :o2.nrec].clone()
+    t_gpu_crop, (Jc, gc) = timed(crop_gradient)
+    gc = gc.cpu().numpy()
+    t0 = time.perf_counter()
+    _, _, tr = oracle.run(c.k64(), c.h, c.nt, s=c.s, src=c.src, rec=c.rec, sponge_width=c.sponge_width,
+                          sponge_alpha=c.sponge_alpha, nthreads=threads)
+    t_orc_fwd = time.perf_counter() - t0
+    _, _, tr_obs = oracle.run(co.k64(), co.h, co.nt, s=co.s, src=co.src, rec=co.rec,
+                              sponge_width=co.sponge_width, sponge_alpha=co.sponge_alpha,
+                              nthreads=threads)
+    r = tr - tr_obs
+    t0 = time.perf_counter()
+    ref = oracle.adjoint(c.k64(), c.h, c.nt, r, s=c.s, src=c.src, rec=c.rec,
+                         sponge_width=c.sponge_width, sponge_alpha=c.sponge_alpha, nthreads=threads)
+    t_orc = time.perf_counter() - t0 + t_orc_fwd
+    e_g = float(np.linalg.norm(gc - ref) / np.linalg.norm(ref))
+    J_ref = 0.5 * float(np.sum(r * r))
+    e_J = abs(Jc.item() - J_ref) / J_ref
+    o2.close()
+    cp.close()
+    log(f"gradient crop 48^3 x {c.nt}: rel-L2 vs oracle {e_g:.3e}, misfit rel {e_J:.2e}; GPU "
+        f"{t_gpu_crop * 1e3:.2f} ms, oracle {t_orc:.2f} s ({threads} threads)")
+    return {"workload": "256^3 x 800 steps FP32, 5 layers 1500-4500 m/s, +5% Gaussian anomaly "
+                        "(sigma 8 cells, seed 2208), data from the model without it, 12 Hz "
+                        "Ricker at (25,128,128), 128 receivers at z=22, 20-cell sponge",
+            "forward_ms": round(t_fwd * 1e3, 3),
+            "gradient_ms": round(t_g50 * 1e3, 3), "checkpoint_every": info50[1],
+            "checkpoint_gb": round(info50[3] / 1e9, 3),
+            "gradient_over_forward": round(t_g50 / t_fwd, 3),
+            "gradient_ms_all_levels": round(t_all * 1e3, 3),
+            "all_levels_gb": round(info_all[3] / 1e9, 3),
+            "all_levels_over_forward": round(t_all / t_fwd, 3),
+            "gradient_gpts_per_s": round(gpts / t_g50, 3),
+            "bitwise_equal_across_checkpointing": same, "finite": finite,
+            "misfit": J50.item(),
+            "crop": {"workload": "48^3 block around the anomaly, 8-cell sponge, 300 steps, "
+                                 "28 receivers, checkpoints every 50",
+                     "rel_l2_gradient_vs_oracle": e_g, "rel_misfit_vs_oracle": e_J,
+                     "gpu_ms": round(t_gpu_crop * 1e3, 3), "oracle_s": round(t_orc, 3),
+                     "oracle_threads": threads,
+                     "speedup_vs_oracle": round(t_orc / t_gpu_crop, 1)},
+            "repeats": reps}
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -250,6 +377,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16 storage forms")
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-shot batched run")
+    ap.add_argument("--no-gradient", action="store_true", help="skip the adjoint gradient leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
 
@@ -335,6 +463,14 @@ def main() -> int:
             log("error: batched traces differ from the sequential runs")
             return 1
 
+    gradient = None
+    if not args.no_gradient and args.workload == "large_shot":
+        prop.close()
+        gradient = gradient_leg(max(2, args.steps), len(os.sched_getaffinity(0)))
+        if not (gradient["finite"] and gradient["bitwise_equal_across_checkpointing"]):
+            log("error: gradient not finite or dependent on the checkpoint interval")
+            return 1
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, args.cpu_seconds)
@@ -366,6 +502,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "forms": forms,
         "batched": batched,
+        "gradient": gradient,
     }
     prop.close()
     print(json.dumps(rec), flush=True)

@@ -160,6 +160,59 @@ int wave_config(const wave_ctx *ctx, int32_t *variant, int32_t *zchunk, int32_t 
 int wave_sync(wave_ctx *ctx);
 
 /*
+ * Gradient with respect to k (FP32 storage only).  The paper gives only the
+ * forward time loop (Eq. 2, Algorithm 1); what follows is the exact discrete
+ * adjoint of that loop as this library runs it (sponge included, source
+ * values held fixed).  For a scalar J of the traces of nt steps, with
+ * g_n = dJ/d trace[n] (one row per step), it returns
+ *
+ *   dJ/dk = sum_{m=1..nt} lambda^m G lap(a^{m-1}),
+ *   lambda^m = R^T g_{m-1} + 2 G lambda^{m+1} + lap(k G lambda^{m+1}) - G^2 lambda^{m+2},
+ *
+ * (lambda^{nt+1} = lambda^{nt+2} = 0, a^m the forward field after step m,
+ * a^0 and a^{-1} the fields the run started from, R^T adding each
+ * receiver's value at its cell).  On the device the adjoint field is kept
+ * as phi = k lambda, so that the adjoint step is the forward stencil update
+ * applied to G phi; every forward level a^{m-1} is recomputed segment by
+ * segment from checkpoints (a^{c-1}, a^c) taken every C steps, and the sum
+ * is accumulated in FP64.  dJ/dv follows as 2 v dt^2 dJ/dk.
+ */
+
+/* Run nt forward steps from the current state, exactly as wave_run (same
+ * traces, fields and step counter afterwards), and keep what the adjoint
+ * run needs: checkpoints every `every` steps (0: the library picks the
+ * largest segment that fits in half of the free device memory -- all levels
+ * of the run when they fit, so that nothing is recomputed) and the levels
+ * of the last segment.  src_dev: nt FP32 device values (copied; NULL = no
+ * source).  Library-owned device memory: (2 ceil(nt / C) + C) field levels
+ * of wave_layout bytes each, kept until the next call or wave_destroy.
+ * WAVE_ENOMEM when it cannot be allocated, WAVE_EINVAL for 16-bit storage. */
+int wave_forward_checkpointed(wave_ctx *ctx, int32_t nt, const float *src_dev, int32_t every);
+
+/* Adjoint run of the last wave_forward_checkpointed run.
+ *   trace_grad_dev  FP32 device array [nt][nrec]: dJ/d trace (row n belongs
+ *                   to step n of that run; may be NULL without receivers);
+ *   grad_dev        FP64 device array [nz][ny][nx] (dense, x fastest):
+ *                   receives dJ/dk, or has it added when accumulate != 0.
+ * Receivers sharing a cell contribute the sum of their derivatives.  May be
+ * called again for another trace_grad of the same run (levels are then
+ * recomputed).  Library-owned device memory: two FP32 fields and one FP64
+ * field of the layout, kept until wave_destroy.  The context's fields,
+ * traces and step counter are left as the forward run left them. */
+int wave_adjoint(wave_ctx *ctx, const float *trace_grad_dev, double *grad_dev, int32_t accumulate);
+
+/* Steps, segment length, segments and bytes of checkpoint/level storage of
+ * the last checkpointed forward run (nt = 0 when there is none). */
+int wave_grad_info(const wave_ctx *ctx, int32_t *nt, int32_t *every, int32_t *segments, int64_t *bytes);
+
+/* Least-squares misfit of n trace values: *misfit_dev = 0.5 sum (t - d)^2,
+ * summed in FP64 in a fixed order (deterministic); residual_dev (FP32, may
+ * be NULL) receives t - d, which is dJ/d trace for this J.  All pointers
+ * are device memory; enqueued on `stream`. */
+int wave_misfit(const float *traces_dev, const float *observed_dev, int64_t n, float *residual_dev,
+                double *misfit_dev, void *stream);
+
+/*
  * Batched runs: many shots (contexts) advanced together, one launch per
  * time step for every group of shots that share a kernel variant and
  * storage type (a work-group finds its shot through a per-launch table).

@@ -84,7 +84,7 @@ struct Coefs {
 struct StepArgs {
     const void *k;
     const void *cur;
-    void *nxt;  // holds u^{n-1} on entry, u^{n+1} on exit (same cells, same thread)
+    void *nxt;  // u^{n-1} (adjoint: phi^{m+2}; imaging: phi^m)
     const float *__restrict__ gx;
     const float *__restrict__ gy;
     const float *__restrict__ gz;
@@ -107,7 +107,21 @@ struct StepArgs {
     float k_scale;            // k = stored k * k_scale
     int *exps;                // [4] exponent of u^m in slot m & 3
     unsigned *maxes;          // [4] max |u^m| (float bits) in slot m & 3
+    // output field: == nxt for the in-place step (each cell is read, then
+    // written, by the same thread), a separate level otherwise
+    void *out;
+    // imaging only: FP64 accumulator in the field layout (8-byte cells)
+    double *grad;
 };
+
+// What a tiled launch computes (FP32 storage only for the last two):
+//   kFwd  u^{n+1} = G (2 u^n - G u^{n-1} + k lap u^n) (+ source, receivers);
+//   kAdj  the adjoint step phi^m = 2 psi + k lap psi - G^2 phi^{m+2} with
+//         psi = G phi^{m+1} (G applied to every loaded value);
+//   kImg  grad += (phi / k) G lap a: the imaging term of one adjoint step.
+constexpr int kFwd = 0;
+constexpr int kAdj = 1;
+constexpr int kImg = 2;
 
 __device__ __forceinline__ float src_value(const StepArgs &a)
 {
@@ -337,7 +351,7 @@ __device__ __forceinline__ void sample_receivers(const StepArgs &a, int lid, int
         return;
     __syncthreads();
     for (int i = r0 + tid; i < r1; i += nt)
-        a.trace_row[a.rec_idx[i]] = read_elem<KIND>(a.nxt, a.rec_off[i], scale);
+        a.trace_row[a.rec_idx[i]] = read_elem<KIND>(a.out, a.rec_off[i], scale);
 }
 
 // Calls f(integral_constant<int, S>) for S = B, B+1, ... < E while f
@@ -357,7 +371,7 @@ __device__ __forceinline__ void static_for_while(F &&f)
 
 // One work-group's share of a step: the tile and z-chunk numbered `lid`
 // (tiles x fastest, then y, then chunks) of the grid described by `a`.
-template <int KIND, int TXV, int TY, int RY>
+template <int KIND, int TXV, int TY, int RY, int MODE = kFwd>
 __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
 {
     constexpr int NT = TXV * TY;
@@ -369,6 +383,8 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
     constexpr int QS = 10;                   // queue slots: 9 live planes + 1 being filled
     constexpr unsigned EB = Store<KIND>::bytes;
     constexpr bool SCALED = Store<KIND>::scaled;
+    constexpr bool ADJ = MODE == kAdj, IMG = MODE == kImg;
+    static_assert(MODE == kFwd || KIND == WAVE_F32, "adjoint and imaging steps are FP32 only");
     __shared__ f4 lds[2][LH][LW];
 
     const int tx = lid % a.ntx;
@@ -436,6 +452,32 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
         const bool ok = use && gy >= -kGhost && gy < a.ny + kGhost && gq >= -1 && gq <= a.nxq;
         h_b[h] = ok ? EB * unsigned((gy + kGhost) * a.px + a.x0 + 4 * gq) : kOff;
     }
+    // adjoint: sponge factor g_x g_y of every cell this thread loads
+    // (cells outside the interior hold zeros; their factor is irrelevant)
+    f4 gh[ADJ ? HPT : 1];
+    if constexpr (ADJ) {
+#pragma unroll
+        for (int h = 0; h < HPT; ++h) {
+            const int i = tid + h * NT;
+            int hr, hc;
+            if (i < 8 * TXV) {
+                const int band = i / TXV;
+                hr = band < 4 ? band - 4 : TYR + band - 4;
+                hc = i % TXV;
+            } else {
+                const int j = i - 8 * TXV;
+                hr = j % TYR;
+                hc = (j / TYR) ? TXV : -1;
+            }
+            const int gy = y0 + hr;
+            const float fy = (gy >= 0 && gy < a.ny) ? a.gy[gy] : 0.f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gxi = 4 * (xq0 + hc) + e;
+                gh[h].v[e] = (gxi >= 0 && gxi < a.nx) ? a.gx[gxi] * fy : 0.f;
+            }
+        }
+    }
 
     // sponge factors that do not change along z
     f4 gxv = {{1.f, 1.f, 1.f, 1.f}};
@@ -448,6 +490,14 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
 #pragma unroll
     for (int r = 0; r < RY; ++r)
         gyv[r] = row_int[r] ? a.gy[row[r]] : 1.f;
+    f4 gown[ADJ ? RY : 1];  // adjoint: g_x g_y of the own cells
+    if constexpr (ADJ) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                gown[r].v[e] = gxv.v[e] * gyv[r];
+    }
 
     // source ownership (the value is read once, before the march)
     int src_r = -1, src_e = 0;
@@ -465,6 +515,9 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
         const_cast<float *>(a.gz), (short)0, a.nz * (int)sizeof(float), kRsrcWord3);
 
     // register queue: at phase s the plane z - 4 + i lives in slot (s + i) % QS
+    auto gz_at = [&](int z) {  // g_z, zero outside the interior (reads nothing there)
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(gz_r, 4u * unsigned(z), 0, 0));
+    };
     f4 q[QS][RY];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -472,12 +525,20 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
 #pragma unroll
         for (int r = 0; r < RY; ++r)
             q[i][r] = load4<KIND, kKeep>(rc, own_ld[r], 1.f);
+        if constexpr (ADJ) {
+            const float gzi = gz_at(z0 - 4 + i);
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    q[i][r].v[e] *= gown[r].v[e] * gzi;
+        }
     }
 
     // values of the next plane, loaded one plane ahead into the set of the
     // other parity (no copies, so no wait before the next loads are issued)
     f4 pv[2][RY], kv[2][RY], hv[2][HPT];
-    float gzv[2];
+    float gzv[2], gzq[2];  // g_z of the plane and (adjoint) of the queue plane z + 4
     auto prefetch = [&](int z, int slot, int set) {
         const __amdgpu_buffer_rsrc_t rq = plane_rsrc(a.cur, pbytes, z + 4);
         const __amdgpu_buffer_rsrc_t rp = plane_rsrc(a.nxt, pbytes, z);
@@ -493,6 +554,8 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
         for (int h = 0; h < HPT; ++h)
             hv[set][h] = load4<KIND, kKeep>(rh, h_b[h], 1.f);
         gzv[set] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(gz_r, 4u * z, 0, 0));
+        if constexpr (ADJ)
+            gzq[set] = gz_at(z + 4);
     };
     prefetch(z0, 8, 0);
 
@@ -508,6 +571,20 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
             // next plane (clamped on the last one, whose loads go unused)
             prefetch(min(z + 1, z1 - 1), (s + 9) % QS, cur_set ^ 1);
 
+            if constexpr (ADJ) {
+                // psi = G phi: the plane that just entered the queue (z + 4)
+                // and this plane's halo
+#pragma unroll
+                for (int r = 0; r < RY; ++r)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        q[(s + 8) % QS][r].v[e] *= gown[r].v[e] * gzq[cur_set];
+#pragma unroll
+                for (int h = 0; h < HPT; ++h)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        hv[cur_set][h].v[e] *= gh[h].v[e] * gzv[cur_set];
+            }
             const int b = z & 1;
             f4 *L = &lds[b][0][0];
 #pragma unroll
@@ -530,7 +607,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
                     ycol[j] = L[(ly * RY + j) * LW + lx + 1];
             }
 
-            const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.nxt, pbytes, z);
+            const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.out, pbytes, z);
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
                 const f4 xl = L[(4 + ly * RY + r) * LW + lx];
@@ -572,16 +649,48 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
                         }
                     }
                     const float g = gxv.v[e] * gyv[r] * gzv[cur_set];
-                    float t, pe;
-                    if constexpr (SCALED) {
-                        t = fmaf(kv[cur_set][r].v[e], lap, fd.two_a * ctr.v[e]);
-                        pe = fd.b * pv[cur_set][r].v[e];
+                    if constexpr (IMG) {
+                        // imaging term: (phi / k) G lap a
+                        out.v[e] = pv[cur_set][r].v[e] / kv[cur_set][r].v[e] * g * lap;
+                    } else if constexpr (ADJ) {
+                        const float t = fmaf(kv[cur_set][r].v[e], lap, 2.f * ctr.v[e]);
+                        out.v[e] = fmaf(-g * g, pv[cur_set][r].v[e], t);
                     } else {
-                        t = fmaf(kv[cur_set][r].v[e], lap, 2.f * ctr.v[e]);
-                        pe = pv[cur_set][r].v[e];
+                        float t, pe;
+                        if constexpr (SCALED) {
+                            t = fmaf(kv[cur_set][r].v[e], lap, fd.two_a * ctr.v[e]);
+                            pe = fd.b * pv[cur_set][r].v[e];
+                        } else {
+                            t = fmaf(kv[cur_set][r].v[e], lap, 2.f * ctr.v[e]);
+                            pe = pv[cur_set][r].v[e];
+                        }
+                        t = fmaf(-g, pe, t);
+                        out.v[e] = g * t;
                     }
-                    t = fmaf(-g, pe, t);
-                    out.v[e] = g * t;
+                }
+                if constexpr (IMG) {
+                    // the accumulator has the field layout with 8-byte cells,
+                    // so a full 4-cell group is two aligned 16-byte pairs
+                    if (col_full) {
+                        double2 *gp = reinterpret_cast<double2 *>(
+                            a.grad + (long long)(z + kGhost) * a.plane + own_in[r] / EB);
+                        if (row_int[r]) {
+                            double2 g0 = gp[0], g1 = gp[1];
+                            g0.x += (double)out.v[0];
+                            g0.y += (double)out.v[1];
+                            g1.x += (double)out.v[2];
+                            g1.y += (double)out.v[3];
+                            gp[0] = g0;
+                            gp[1] = g1;
+                        }
+                    } else if (row_int[r]) {
+                        double *gp = a.grad + (long long)(z + kGhost) * a.plane + own_in[r] / EB;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (x + e < a.nx)
+                                gp[e] += (double)out.v[e];
+                    }
+                    continue;
                 }
                 if (src_r == r && z == a.src_z) {
 #pragma unroll
@@ -624,6 +733,73 @@ __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
     if (lid >= a.nwg)
         return;
     tile_step<KIND, TXV, TY, RY>(a, lid);
+}
+
+template <int MODE, int TXV, int TY, int RY>
+__global__ __launch_bounds__(TXV *TY) void adjoint_tiled(StepArgs a)
+{
+    const int lid = logical_wg();
+    if (lid >= a.nwg)
+        return;
+    tile_step<WAVE_F32, TXV, TY, RY, MODE>(a, lid);
+}
+
+// Adds k * trace_grad[row][r] at the receiver cells: one thread per distinct
+// cell, summing its receivers in a fixed order (deterministic, no atomics).
+__global__ void inject_receivers(float *phi, const float *__restrict__ k, const long long *__restrict__ cell_off,
+                                 const int *__restrict__ cell_start, const int *__restrict__ cell_rec,
+                                 int ncells, const float *__restrict__ tg_row)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncells) {
+        float s = 0.f;
+        for (int i = cell_start[c]; i < cell_start[c + 1]; ++i)
+            s += tg_row[cell_rec[i]];
+        const long long o = cell_off[c];
+        phi[o] = fmaf(k[o], s, phi[o]);
+    }
+}
+
+// misfit = 0.5 sum (traces - d_obs)^2 in FP64 (one work-group, fixed
+// summation order, differences taken exactly); residual = traces - d_obs
+// rounded to FP32 when requested.
+__global__ __launch_bounds__(1024) void misfit_kernel(const float *__restrict__ tr,
+                                                      const float *__restrict__ obs, long long n,
+                                                      float *residual, double *out)
+{
+    __shared__ double part[1024];
+    double acc = 0.0;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+        const double r = (double)tr[i] - (double)obs[i];  // exact
+        if (residual)
+            residual[i] = (float)r;  // == the FP32 difference
+        acc += r * r;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        *out = 0.5 * part[0];
+}
+
+// dense[z][y][x] (+)= acc at the interior cells of the field layout.
+__global__ __launch_bounds__(256) void grad_to_dense(const double *__restrict__ acc, double *dense, int nx,
+                                                    int ny, int nz, int px, int x0, long long plane,
+                                                    int accumulate)
+{
+    const long long n = (long long)nx * ny * nz;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx);
+        const int y = (int)((i / nx) % ny);
+        const int z = (int)(i / ((long long)nx * ny));
+        const double v = acc[(long long)(z + kGhost) * plane + (long long)(y + kGhost) * px + x0 + x];
+        dense[i] = accumulate ? dense[i] + v : v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -681,6 +857,7 @@ __global__ __launch_bounds__(TXV *TY) void step_batch(const ShotDesc *__restrict
             a.cur = a.nxt;
             a.nxt = const_cast<void *>(t);
         }
+        a.out = a.nxt;  // in place
         const int n = d.n0 + j;
         a.step = n & 0x3fffffff;
         a.trace_row = d.traces ? d.traces + (size_t)n * d.nrec : nullptr;
@@ -750,9 +927,9 @@ __global__ __launch_bounds__(256) void step_naive(StepArgs a)
         if (z == a.src_z && y == a.src_y && x == a.src_x)
             v += src_value(a) * sc.out_inv;
         if constexpr (KIND == WAVE_F32) {
-            static_cast<float *>(a.nxt)[p] = v;
+            static_cast<float *>(a.out)[p] = v;
         } else {
-            static_cast<unsigned short *>(a.nxt)[p] = (unsigned short)Store<KIND>::enc(v);
+            static_cast<unsigned short *>(a.out)[p] = (unsigned short)Store<KIND>::enc(v);
             amax = fabsf(v);
         }
     }
@@ -853,6 +1030,7 @@ struct Variant {
     const char *name;
     StepKernel fn[3];  // by storage type; all NULL for "auto" and "naive"
     BatchKernel batch[3];
+    StepKernel adj[2];  // adjoint step, imaging step (FP32)
     int txv, ty, ry;
 };
 
@@ -860,11 +1038,12 @@ struct Variant {
     {step_tiled<WAVE_F32, TXV, TY, RY>, step_tiled<WAVE_F16, TXV, TY, RY>,                        \
      step_tiled<WAVE_BF16, TXV, TY, RY>},                                                         \
     {step_batch<WAVE_F32, TXV, TY, RY>, step_batch<WAVE_F16, TXV, TY, RY>,                        \
-     step_batch<WAVE_BF16, TXV, TY, RY>}
+     step_batch<WAVE_BF16, TXV, TY, RY>},                                                         \
+    {adjoint_tiled<kAdj, TXV, TY, RY>, adjoint_tiled<kImg, TXV, TY, RY>}
 
 const Variant kVariants[] = {
-    {"auto", {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, 0, 0, 0},
-    {"naive", {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, 0, 0, 0},
+    {"auto", {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr}, 0, 0, 0},
+    {"naive", {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr}, 0, 0, 0},
     {"t64x16_r1", TILED(16, 16, 1), 16, 16, 1},
     {"t128x8_r1", TILED(32, 8, 1), 32, 8, 1},
     {"t128x16_r2", TILED(32, 8, 2), 32, 8, 2},
@@ -885,7 +1064,34 @@ const StepKernel kNaiveFn[3] = {step_naive<WAVE_F32>, step_naive<WAVE_F16>, step
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// Launch geometry of a tiled (or the naive) kernel over one grid.
+struct Geo {
+    int v = 0, ntx = 0, nty = 0, nchunks = 0, zc = 0, nwg = 0, grid = 0;
+};
+
 }  // namespace
+
+// State of the gradient computation (FP32 storage): the checkpoints and the
+// level store of the last checkpointed forward run, the adjoint fields and
+// the FP64 accumulator, all in the field layout (ghost cells zero).
+struct wave_grad_state {
+    int64_t step0 = 0;  // step counter at the start of the forward run
+    int nt = 0;         // steps of the run (0: no run recorded)
+    int every = 0;      // segment length C
+    int nseg = 0;       // segments: segment i covers steps i*C .. min((i+1)*C, nt) - 1
+    int held = -1;      // segment whose levels c+1 .. the store holds
+    bool has_src = false;
+    void *slab = nullptr;  // 2 * nseg checkpoint levels, then C store levels
+    size_t slab_levels = 0;
+    float *src = nullptr;  // the run's source values [nt]
+    int src_cap = 0;
+    void *phi[2] = {nullptr, nullptr};
+    double *acc = nullptr;
+    // receiver cells (distinct) and, per cell, its receivers
+    long long *cell_off = nullptr;
+    int *cell_start = nullptr, *cell_rec = nullptr;
+    int ncells = -1;
+};
 
 struct wave_ctx {
     wave_params_t p;
@@ -916,6 +1122,7 @@ struct wave_ctx {
     int variant = 0, zchunk = 0;  // requested (0 = auto)
     int v_used = 0, zc_used = 0;
     int ntx = 0, nty = 0, nchunks = 0, nwg = 0, grid = 0;
+    wave_grad_state g;
     std::string err;
 };
 
@@ -966,28 +1173,28 @@ constexpr int kSmallVariant = 2;    // t64x16_r1 for grids of fewer than 2^22 ce
 constexpr int kTargetWorkgroups = 256;
 constexpr int kMinChunk = 32;
 
-void plan_launch(wave_ctx *c)
+Geo plan_geo(int nx, int ny, int nz, int variant, int zchunk)
 {
-    const int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
-    int v = c->variant;
+    Geo g;
+    int v = variant;
     if (v == 0) {
         const long long pts = (long long)nx * ny * nz;
         v = pts >= (1ll << 22) ? kAutoVariant : kSmallVariant;
     }
-    c->v_used = v;
+    g.v = v;
     if (v == kNaive) {
-        c->ntx = c->nty = c->nchunks = 0;
-        c->zc_used = nz;
+        g.ntx = g.nty = g.nchunks = 0;
+        g.zc = nz;
         long long n = (long long)nx * ny * nz;
-        c->nwg = c->grid = int((n + 255) / 256);
-        return;
+        g.nwg = g.grid = int((n + 255) / 256);
+        return g;
     }
     const Variant &V = kVariants[v];
     const int tx = 4 * V.txv, tyr = V.ty * V.ry;
-    c->ntx = (nx + tx - 1) / tx;
-    c->nty = (ny + tyr - 1) / tyr;
-    const long long tiles = (long long)c->ntx * c->nty;
-    int zc = c->zchunk;
+    g.ntx = (nx + tx - 1) / tx;
+    g.nty = (ny + tyr - 1) / tyr;
+    const long long tiles = (long long)g.ntx * g.nty;
+    int zc = zchunk;
     if (zc <= 0) {
         const long long chunks = std::max(1ll, (kTargetWorkgroups + tiles / 2) / tiles);
         zc = int((nz + chunks - 1) / chunks);
@@ -995,10 +1202,23 @@ void plan_launch(wave_ctx *c)
     }
     if (zc > nz)
         zc = nz;
-    c->zc_used = zc;
-    c->nchunks = (nz + zc - 1) / zc;
-    c->nwg = int(tiles * c->nchunks);
-    c->grid = int(round_up(c->nwg, 8));
+    g.zc = zc;
+    g.nchunks = (nz + zc - 1) / zc;
+    g.nwg = int(tiles * g.nchunks);
+    g.grid = int(round_up(g.nwg, 8));
+    return g;
+}
+
+void plan_launch(wave_ctx *c)
+{
+    const Geo g = plan_geo(c->p.nx, c->p.ny, c->p.nz, c->variant, c->zchunk);
+    c->v_used = g.v;
+    c->ntx = g.ntx;
+    c->nty = g.nty;
+    c->nchunks = g.nchunks;
+    c->zc_used = g.zc;
+    c->nwg = g.nwg;
+    c->grid = g.grid;
 }
 
 long long elem_offset(const wave_layout_t &l, int z, int y, int x)
@@ -1085,14 +1305,24 @@ StepArgs make_args(const wave_ctx *c)
     a.k_scale = c->k_scale;
     a.exps = c->ring;
     a.maxes = reinterpret_cast<unsigned *>(c->ring + 4);
+    a.out = c->prev;
+    a.grad = nullptr;
     return a;
 }
 
-int launch_step(wave_ctx *c, const float *src_ptr, float src_val)
+// One forward step from (cur = u^n, prev = u^{n-1}) into `out` (== prev for
+// the in-place step), step counter and trace row as given.
+int enqueue_forward(wave_ctx *c, void *cur, void *prev, void *out, const float *src_ptr, float src_val,
+                    int64_t step, float *trace_row)
 {
     StepArgs a = make_args(c);
+    a.cur = cur;
+    a.nxt = prev;
+    a.out = out;
     a.src_ptr = src_ptr;
     a.src_val = src_val;
+    a.step = int(step & 0x3fffffff);
+    a.trace_row = trace_row;
 
     const int kind = c->p.dtype;
     if (c->v_used == kNaive) {
@@ -1100,7 +1330,7 @@ int launch_step(wave_ctx *c, const float *src_ptr, float src_val)
         if (a.trace_row) {
             const dim3 g((c->nrec + 255) / 256), b(256);
             const int slot = (a.step + 1) & 3;
-            const void *f = c->prev;
+            const void *f = out;
             const long long *off = c->rec_off_all;
             const int *ex = c->ring;
             if (kind == WAVE_F32)
@@ -1120,6 +1350,20 @@ int launch_step(wave_ctx *c, const float *src_ptr, float src_val)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return fail(c, WAVE_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return WAVE_OK;
+}
+
+float *trace_row_of(const wave_ctx *c, int64_t step)
+{
+    return (c->traces && c->nrec > 0) ? c->traces + (size_t)step * c->nrec : nullptr;
+}
+
+int launch_step(wave_ctx *c, const float *src_ptr, float src_val)
+{
+    const int rc = enqueue_forward(c, c->cur, c->prev, c->prev, src_ptr, src_val, c->step,
+                                   trace_row_of(c, c->step));
+    if (rc != WAVE_OK)
+        return rc;
     // u^{n+1} now lives in the old u^{n-1} buffer
     void *t = c->prev;
     c->prev = c->cur;
@@ -1136,8 +1380,22 @@ int check_trace_room(wave_ctx *c, int64_t nsteps)
     return WAVE_OK;
 }
 
+void free_grad(wave_grad_state &g)
+{
+    free_dev(g.slab);
+    free_dev(g.src);
+    free_dev(g.phi[0]);
+    free_dev(g.phi[1]);
+    free_dev(g.acc);
+    free_dev(g.cell_off);
+    free_dev(g.cell_start);
+    free_dev(g.cell_rec);
+    g = wave_grad_state();
+}
+
 void free_device(wave_ctx *c)
 {
+    free_grad(c->g);
     free_dev(c->gx);
     free_dev(c->gy);
     free_dev(c->gz);
@@ -1175,6 +1433,135 @@ int launch_convert(hipStream_t s, int src_kind, int dst_kind, const void *src, v
         return WAVE_EINVAL;
 #undef CONV
     return hipGetLastError() == hipSuccess ? WAVE_OK : WAVE_EHIP;
+}
+
+// ---------------------------------------------------------------------------
+// gradient with respect to k: checkpointed forward run, adjoint run
+
+Geo ctx_geo(const wave_ctx *c)
+{
+    Geo g;
+    g.v = c->v_used;
+    g.ntx = c->ntx;
+    g.nty = c->nty;
+    g.nchunks = c->nchunks;
+    g.zc = c->zc_used;
+    g.nwg = c->nwg;
+    g.grid = c->grid;
+    return g;
+}
+
+// The adjoint and imaging steps use the context's tiling (the automatic one
+// when the context runs the naive kernel).
+Geo adjoint_geo(const wave_ctx *c)
+{
+    return c->v_used == kNaive ? plan_geo(c->p.nx, c->p.ny, c->p.nz, 0, 0) : ctx_geo(c);
+}
+
+int enqueue_adjoint(wave_ctx *c, const Geo &geo, int mode, const void *cur, void *nxt, void *out,
+                    double *acc)
+{
+    StepArgs a = make_args(c);
+    a.cur = cur;
+    a.nxt = nxt;
+    a.out = out;
+    a.grad = acc;
+    a.ntx = geo.ntx;
+    a.nty = geo.nty;
+    a.nchunks = geo.nchunks;
+    a.zc = geo.zc;
+    a.nwg = geo.nwg;
+    a.src_z = a.src_y = a.src_x = -1;
+    a.src_ptr = nullptr;
+    a.trace_row = nullptr;
+    const Variant &V = kVariants[geo.v];
+    hipLaunchKernelGGL(V.adj[mode - 1], dim3(geo.grid), dim3(V.txv * V.ty), 0, c->stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(c, WAVE_EHIP, "adjoint launch failed: %s", hipGetErrorString(e));
+    return WAVE_OK;
+}
+
+size_t level_bytes(const wave_ctx *c) { return (size_t)c->lay.bytes; }
+
+// Level l of segment `seg`: a^{c-1} and a^c from the checkpoint, a^{c+1} ..
+// a^{c+C} from the store (c = seg * C).
+void *level_ptr(wave_ctx *c, int seg, int64_t l)
+{
+    wave_grad_state &g = c->g;
+    const int64_t c0 = (int64_t)seg * g.every;
+    char *base = static_cast<char *>(g.slab);
+    const size_t lb = level_bytes(c);
+    if (l <= c0)
+        return base + lb * (size_t)(2 * seg + (l == c0 ? 1 : 0));
+    return base + lb * (size_t)(2 * g.nseg + (l - c0 - 1));
+}
+
+// Out-of-place forward steps of segment `seg` from its checkpoint, writing
+// levels c+1 .. c+count into the store; traces are written when `record`.
+int forward_segment(wave_ctx *c, int seg, int count, bool record)
+{
+    wave_grad_state &g = c->g;
+    const int64_t c0 = (int64_t)seg * g.every;
+    for (int j = 0; j < count; ++j) {
+        const int64_t n = c0 + j;  // this step writes a^{n+1}
+        const float *sp = g.has_src ? g.src + n : nullptr;
+        const int rc = enqueue_forward(c, level_ptr(c, seg, n), level_ptr(c, seg, n - 1),
+                                       level_ptr(c, seg, n + 1), sp, 0.f, g.step0 + n,
+                                       record ? trace_row_of(c, g.step0 + n) : nullptr);
+        if (rc != WAVE_OK)
+            return rc;
+    }
+    g.held = seg;
+    return WAVE_OK;
+}
+
+// Distinct receiver cells with their receivers (the adjoint source adds the
+// trace derivatives of every receiver at a cell).
+int build_receiver_cells(wave_ctx *c)
+{
+    wave_grad_state &g = c->g;
+    if (g.ncells >= 0)
+        return WAVE_OK;
+    std::vector<std::pair<long long, int>> r(c->nrec);
+    for (int i = 0; i < c->nrec; ++i)
+        r[i] = {elem_offset(c->lay, c->rec[3 * i], c->rec[3 * i + 1], c->rec[3 * i + 2]), i};
+    std::sort(r.begin(), r.end());
+    std::vector<long long> off;
+    std::vector<int> start, idx;
+    for (int i = 0; i < c->nrec; ++i) {
+        if (i == 0 || r[i].first != r[i - 1].first) {
+            off.push_back(r[i].first);
+            start.push_back(i);
+        }
+        idx.push_back(r[i].second);
+    }
+    start.push_back(c->nrec);
+    g.ncells = int(off.size());
+    off.resize(std::max<size_t>(off.size(), 1));
+    idx.resize(std::max<size_t>(idx.size(), 1));
+    HIP_TRY(c, hipMalloc(&g.cell_off, sizeof(long long) * off.size()));
+    HIP_TRY(c, hipMalloc(&g.cell_start, sizeof(int) * start.size()));
+    HIP_TRY(c, hipMalloc(&g.cell_rec, sizeof(int) * idx.size()));
+    HIP_TRY(c, hipMemcpy(g.cell_off, off.data(), sizeof(long long) * off.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(g.cell_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(g.cell_rec, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice));
+    return WAVE_OK;
+}
+
+// Segment length when the caller leaves it to the library: every level of
+// the run when that fits in half of the free device memory, else the
+// largest C whose checkpoints and store (2 ceil(nt / C) + C levels) fit.
+int auto_segment(const wave_ctx *c, int nt)
+{
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess)
+        return -1;
+    const double budget = 0.5 * double(free_b) / double(level_bytes(c));
+    for (int C = nt; C >= 1; --C)
+        if (2.0 * ((nt + C - 1) / C) + C <= budget)
+            return C;
+    return -1;
 }
 
 }  // namespace
@@ -1545,6 +1932,170 @@ int wave_destroy(wave_ctx *ctx)
     free_device(ctx);
     delete ctx;
     return WAVE_OK;
+}
+
+int wave_forward_checkpointed(wave_ctx *ctx, int32_t nt, const float *src_dev, int32_t every)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    if (ctx->p.dtype != WAVE_F32)
+        return fail(ctx, WAVE_EINVAL, "the gradient is available for FP32 storage only");
+    if (nt < 1 || every < 0)
+        return fail(ctx, WAVE_EINVAL, "nt must be >= 1 and every >= 0");
+    int rc = check_trace_room(ctx, nt);
+    if (rc != WAVE_OK)
+        return rc;
+    int C = every > 0 ? std::min(every, nt) : auto_segment(ctx, nt);
+    if (C < 1)
+        return fail(ctx, WAVE_ENOMEM, "not enough device memory for the checkpoints of %d steps", nt);
+    wave_grad_state &g = ctx->g;
+    const int nseg = (nt + C - 1) / C;
+    const size_t levels = 2 * (size_t)nseg + (size_t)C;
+    g.nt = 0;  // invalid until the run is enqueued
+    if (levels > g.slab_levels) {
+        free_dev(g.slab);
+        g.slab_levels = 0;
+        if (hipMalloc(&g.slab, levels * level_bytes(ctx)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, WAVE_ENOMEM, "cannot allocate %zu field levels (%.2f GB)", levels,
+                        levels * double(level_bytes(ctx)) / 1e9);
+        }
+        g.slab_levels = levels;
+        // ghost cells stay zero: steps write interior cells only
+        HIP_TRY(ctx, hipMemsetAsync(g.slab, 0, levels * level_bytes(ctx), ctx->stream));
+    }
+    if (src_dev) {
+        if (nt > g.src_cap) {
+            free_dev(g.src);
+            g.src_cap = 0;
+            HIP_TRY(ctx, hipMalloc(&g.src, sizeof(float) * (size_t)nt));
+            g.src_cap = nt;
+        }
+        HIP_TRY(ctx, hipMemcpyAsync(g.src, src_dev, sizeof(float) * (size_t)nt,
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    g.has_src = src_dev != nullptr;
+    g.step0 = ctx->step;
+    g.every = C;
+    g.nseg = nseg;
+    g.held = -1;
+
+    const size_t lb = level_bytes(ctx);
+    for (int seg = 0; seg < nseg; ++seg) {
+        const int64_t c0 = (int64_t)seg * C;
+        const int len = int(std::min<int64_t>(C, nt - c0));
+        HIP_TRY(ctx, hipMemcpyAsync(level_ptr(ctx, seg, c0 - 1), ctx->prev, lb, hipMemcpyDeviceToDevice,
+                                    ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(level_ptr(ctx, seg, c0), ctx->cur, lb, hipMemcpyDeviceToDevice,
+                                    ctx->stream));
+        if (seg + 1 < nseg) {
+            for (int j = 0; j < len; ++j) {
+                rc = launch_step(ctx, g.has_src ? g.src + c0 + j : nullptr, 0.f);
+                if (rc != WAVE_OK)
+                    return rc;
+            }
+        } else {
+            // the last segment keeps its levels for the adjoint run
+            rc = forward_segment(ctx, seg, len, true);
+            if (rc != WAVE_OK)
+                return rc;
+            HIP_TRY(ctx, hipMemcpyAsync(ctx->prev, level_ptr(ctx, seg, c0 + len - 1), lb,
+                                        hipMemcpyDeviceToDevice, ctx->stream));
+            HIP_TRY(ctx, hipMemcpyAsync(ctx->cur, level_ptr(ctx, seg, c0 + len), lb,
+                                        hipMemcpyDeviceToDevice, ctx->stream));
+            ctx->step += len;
+        }
+    }
+    g.nt = nt;
+    return WAVE_OK;
+}
+
+int wave_adjoint(wave_ctx *ctx, const float *trace_grad_dev, double *grad_dev, int32_t accumulate)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    wave_grad_state &g = ctx->g;
+    if (g.nt < 1)
+        return fail(ctx, WAVE_ESTATE, "wave_adjoint needs a preceding wave_forward_checkpointed");
+    if (!grad_dev || (ctx->nrec > 0 && !trace_grad_dev))
+        return fail(ctx, WAVE_EINVAL, "wave_adjoint: grad and (with receivers) trace_grad are required");
+    int rc = build_receiver_cells(ctx);
+    if (rc != WAVE_OK)
+        return rc;
+    const size_t lb = level_bytes(ctx);
+    const size_t ab = (size_t)ctx->lay.elems * sizeof(double);
+    for (int i = 0; i < 2; ++i)
+        if (!g.phi[i]) {
+            HIP_TRY(ctx, hipMalloc(&g.phi[i], lb));
+        }
+    if (!g.acc) {
+        HIP_TRY(ctx, hipMalloc(&g.acc, ab));
+    }
+    HIP_TRY(ctx, hipMemsetAsync(g.phi[0], 0, lb, ctx->stream));
+    HIP_TRY(ctx, hipMemsetAsync(g.phi[1], 0, lb, ctx->stream));
+    HIP_TRY(ctx, hipMemsetAsync(g.acc, 0, ab, ctx->stream));
+
+    const Geo geo = adjoint_geo(ctx);
+    void *A = g.phi[0], *B = g.phi[1];  // phi^{m+1}, phi^{m+2}
+    for (int m = g.nt; m >= 1; --m) {
+        // phi^m = 2 G phi^{m+1} + K L G phi^{m+1} - G^2 phi^{m+2}, over phi^{m+2}
+        rc = enqueue_adjoint(ctx, geo, kAdj, A, B, B, nullptr);
+        if (rc != WAVE_OK)
+            return rc;
+        std::swap(A, B);
+        // + K R^T (dJ/d traces row m-1)
+        if (g.ncells > 0) {
+            hipLaunchKernelGGL(inject_receivers, dim3((g.ncells + 255) / 256), dim3(256), 0, ctx->stream,
+                               static_cast<float *>(A), static_cast<const float *>(ctx->k), g.cell_off,
+                               g.cell_start, g.cell_rec, g.ncells,
+                               trace_grad_dev + (size_t)(m - 1) * ctx->nrec);
+            HIP_TRY(ctx, hipGetLastError());
+        }
+        // grad += (phi^m / k) G L a^{m-1}
+        const int seg = (m - 1) / g.every;
+        if (g.held != seg) {
+            const int64_t c0 = (int64_t)seg * g.every;
+            rc = forward_segment(ctx, seg, int(std::min<int64_t>(g.every, g.nt - c0)) - 1, false);
+            if (rc != WAVE_OK)
+                return rc;
+        }
+        rc = enqueue_adjoint(ctx, geo, kImg, level_ptr(ctx, seg, m - 1), A, nullptr, g.acc);
+        if (rc != WAVE_OK)
+            return rc;
+    }
+    const long long n = (long long)ctx->p.nx * ctx->p.ny * ctx->p.nz;
+    hipLaunchKernelGGL(grad_to_dense, dim3((unsigned)std::min<long long>((n + 255) / 256, 8192)), dim3(256),
+                       0, ctx->stream, g.acc, grad_dev, ctx->p.nx, ctx->p.ny, ctx->p.nz,
+                       int(ctx->lay.pitch_x), int(ctx->lay.x_offset), (long long)ctx->lay.plane,
+                       accumulate ? 1 : 0);
+    HIP_TRY(ctx, hipGetLastError());
+    return WAVE_OK;
+}
+
+int wave_grad_info(const wave_ctx *ctx, int32_t *nt, int32_t *every, int32_t *segments, int64_t *bytes)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    const wave_grad_state &g = ctx->g;
+    if (nt)
+        *nt = g.nt;
+    if (every)
+        *every = g.every;
+    if (segments)
+        *segments = g.nseg;
+    if (bytes)
+        *bytes = int64_t(g.slab_levels * level_bytes(ctx));
+    return WAVE_OK;
+}
+
+int wave_misfit(const float *traces_dev, const float *observed_dev, int64_t n, float *residual_dev,
+                double *misfit_dev, void *stream)
+{
+    if (n < 0 || !misfit_dev || (n > 0 && (!traces_dev || !observed_dev)))
+        return WAVE_EINVAL;
+    hipLaunchKernelGGL(misfit_kernel, dim3(1), dim3(1024), 0, static_cast<hipStream_t>(stream), traces_dev,
+                       observed_dev, (long long)n, residual_dev, misfit_dev);
+    return hipGetLastError() == hipSuccess ? WAVE_OK : WAVE_EHIP;
 }
 
 int wave_batch_create(wave_batch **out, wave_ctx *const *ctxs, int32_t nshots, void *stream,

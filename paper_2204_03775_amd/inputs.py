@@ -24,6 +24,15 @@ The paper runs on synthetic grids whose velocity model it does not state
   large-shot model, its own 20-cell sponge, 500 steps, source at
   (25, 64, 64), 88 receivers at z = 22, y = 64, x = 20..107 (accuracy of
   the reduced-precision storage forms).
+* ``gradient_shot``: 256^3, 800 steps, five equal layers 1500..4500 m/s
+  (no noise) for the observed data; the evaluation model adds a Gaussian
+  anomaly of +5 % (sigma 8 cells) centred at a point drawn (seed 2208) in
+  the middle third of every axis; 20-cell sponge, 12 Hz Ricker at
+  (25, 128, 128), 128 receivers at z = 22, y = 128, x = 20..235;
+  checkpoints every 50 steps (gradient of the least-squares misfit).
+* ``gradient_crop``: the 48^3 block of both models centred on the anomaly,
+  8-cell sponge (alpha 0.04), 300 steps, source at (12, 24, 24),
+  28 receivers at z = 10, y = 24, x = 10..37 (checks of the gradient).
 
 Random draws use ``numpy.random.default_rng(2204 + i)`` for workload i.
 """
@@ -230,3 +239,64 @@ def random_problem(nx: int, ny: int, nz: int, nt: int, *, seed: int, h=(10.0, 12
     w = ricker(freq, nt, dt, t0=1.2 / freq)
     return Problem(f"random_{nx}x{ny}x{nz}", nx, ny, nz, tuple(h), dt, nt, sponge_width,
                    sponge_alpha, src, rec, point_source_values(w, float(v[src]), dt, h), v)
+
+
+@dataclass
+class GradientProblem:
+    """A shot in an evaluation model (``shot.v``) with data observed in
+    another model (``v_obs``); the gradient is that of the least-squares
+    misfit 0.5 || traces(v) - traces(v_obs) ||^2 with respect to k."""
+
+    shot: Problem
+    v_obs: np.ndarray = field(repr=False)
+    every: int
+    anomaly: tuple
+
+    def observed(self) -> Problem:
+        p = self.shot
+        return Problem(p.name + "_obs", p.nx, p.ny, p.nz, p.h, p.dt, p.nt, p.sponge_width,
+                       p.sponge_alpha, p.src, p.rec, p.s, self.v_obs)
+
+
+_GRAD_MODELS = {}
+
+
+def gradient_models(n: int = 256):
+    """(layered model, model with the anomaly, anomaly centre), float32."""
+    if n not in _GRAD_MODELS:
+        base = layered_velocity(n, n, n, [1500.0, 2250.0, 3000.0, 3750.0, 4500.0])
+        rng = np.random.default_rng(2208)
+        c = tuple(int(rng.integers(n // 3, 2 * n // 3)) for _ in range(3))
+        z, y, x = np.ogrid[:n, :n, :n]
+        r2 = (z - c[0]) ** 2 + (y - c[1]) ** 2 + (x - c[2]) ** 2
+        bump = np.exp(-r2 / (2.0 * 8.0 ** 2))
+        ev = (base.astype(np.float64) * (1.0 + 0.05 * bump)).astype(np.float32)
+        _GRAD_MODELS[n] = (base, ev, c)
+    return _GRAD_MODELS[n]
+
+
+def gradient_shot(n: int = 256, nt: int = 800, every: int = 50) -> GradientProblem:
+    h = (10.0, 10.0, 10.0)
+    dt = cfl_dt(4500.0, 10.0, 0.8)
+    base, ev, c = gradient_models(n)
+    src = (25, n // 2, n // 2)
+    w = ricker(12.0, nt, dt)
+    rec = line_receivers(22, n // 2, 20, n - 21, 128)
+    shot = Problem("gradient_shot", n, n, n, h, dt, nt, 20, 0.015, src, rec,
+                   point_source_values(w, float(ev[src]), dt, h), ev)
+    return GradientProblem(shot, base, every, c)
+
+
+def gradient_crop(nt: int = 300, m: int = 48) -> GradientProblem:
+    h = (10.0, 10.0, 10.0)
+    dt = cfl_dt(4500.0, 10.0, 0.8)
+    base, ev, c = gradient_models()
+    sl = tuple(slice(ci - m // 2, ci - m // 2 + m) for ci in c)
+    vb = np.ascontiguousarray(base[sl])
+    ve = np.ascontiguousarray(ev[sl])
+    src = (12, m // 2, m // 2)
+    w = ricker(12.0, nt, dt)
+    rec = np.array([[10, m // 2, x] for x in range(10, m - 10)], dtype=np.int32)
+    shot = Problem("gradient_crop", m, m, m, h, dt, nt, 8, 0.04, src, rec,
+                   point_source_values(w, float(ve[src]), dt, h), ve)
+    return GradientProblem(shot, vb, 50, tuple(m // 2 for _ in range(3)))

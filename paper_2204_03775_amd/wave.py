@@ -76,6 +76,11 @@ def _load():
         "wave_config": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], ci),
         "wave_sync": ([vp], ci),
         "wave_destroy": ([vp], ci),
+        "wave_forward_checkpointed": ([vp, i32, vp, i32], ci),
+        "wave_adjoint": ([vp, vp, vp, i32], ci),
+        "wave_grad_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                            ctypes.POINTER(i64)], ci),
+        "wave_misfit": ([vp, vp, i64, vp, vp, vp], ci),
         "wave_batch_create": ([ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp, i32], ci),
         "wave_batch_run": ([vp, i32, ctypes.POINTER(vp)], ci),
         "wave_batch_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64)], ci),
@@ -196,6 +201,25 @@ def wave_sync(ctx):
 
 def wave_destroy(ctx):
     _check(_lib.wave_destroy(ctx))
+
+
+def wave_forward_checkpointed(ctx, nt: int, src_ptr=None, every: int = 0):
+    _check(_lib.wave_forward_checkpointed(ctx, nt, src_ptr, every), ctx)
+
+
+def wave_adjoint(ctx, trace_grad_ptr, grad_ptr, accumulate: bool = False):
+    _check(_lib.wave_adjoint(ctx, trace_grad_ptr, grad_ptr, int(bool(accumulate))), ctx)
+
+
+def wave_grad_info(ctx):
+    nt, every, seg, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _check(_lib.wave_grad_info(ctx, ctypes.byref(nt), ctypes.byref(every), ctypes.byref(seg),
+                               ctypes.byref(nb)), ctx)
+    return nt.value, every.value, seg.value, nb.value
+
+
+def wave_misfit(traces_ptr, observed_ptr, n: int, residual_ptr, misfit_ptr, stream):
+    _check(_lib.wave_misfit(traces_ptr, observed_ptr, n, residual_ptr, misfit_ptr, stream))
 
 
 def wave_strerror(code: int) -> str:
@@ -337,6 +361,40 @@ class Propagator:
             ptr = src.data_ptr()
         wave_run(self.ctx, int(nsteps), ptr)
 
+    def forward_checkpointed(self, nt: int, src=None, every: int = 0):
+        """``run`` that also keeps what ``adjoint`` needs (checkpoints every
+        ``every`` steps; 0 lets the library choose)."""
+        ptr = None
+        if src is not None:
+            assert src.dtype == torch.float32 and src.is_cuda and src.is_contiguous()
+            assert src.numel() >= nt
+            ptr = src.data_ptr()
+        wave_forward_checkpointed(self.ctx, int(nt), ptr, int(every))
+
+    def adjoint(self, trace_grad=None, grad=None, accumulate: bool = False):
+        """dJ/dk (FP64 [nz][ny][nx] device tensor) of the last checkpointed
+        run, for ``trace_grad`` = dJ/d traces ([nt][nrec] FP32 device)."""
+        ptr = None
+        if self.nrec > 0:
+            assert trace_grad is not None
+            nt = wave_grad_info(self.ctx)[0]  # 0 without a run: the library reports it
+            assert trace_grad.dtype == torch.float32 and trace_grad.is_cuda
+            assert trace_grad.is_contiguous()
+            assert nt == 0 or tuple(trace_grad.shape) == (nt, self.nrec)
+            ptr = trace_grad.data_ptr()
+        if grad is None:
+            grad = torch.zeros((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+            accumulate = False
+        assert grad.dtype == torch.float64 and grad.is_contiguous()
+        assert tuple(grad.shape) == (self.nz, self.ny, self.nx)
+        wave_adjoint(self.ctx, ptr, grad.data_ptr(), accumulate)
+        return grad
+
+    def grad_info(self):
+        """(steps, segment length, segments, checkpoint bytes) of the last
+        checkpointed run."""
+        return wave_grad_info(self.ctx)
+
     def configure(self, variant=0, zchunk=0):
         if isinstance(variant, str):
             variant = variants()[variant]
@@ -414,3 +472,73 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def misfit(traces, observed, stream=None):
+    """(0.5 sum (traces - observed)^2 as an FP64 device scalar, FP32
+    residual traces - observed), both computed by the library."""
+    assert traces.dtype == torch.float32 and observed.dtype == torch.float32
+    assert traces.is_cuda and traces.is_contiguous() and observed.is_contiguous()
+    assert traces.shape == observed.shape
+    stream = stream if stream is not None else torch.cuda.current_stream(traces.device)
+    out = torch.empty((), dtype=torch.float64, device=traces.device)
+    res = torch.empty_like(traces)
+    wave_misfit(traces.data_ptr(), observed.data_ptr(), traces.numel(), res.data_ptr(),
+                out.data_ptr(), stream.cuda_stream)
+    return out, res
+
+
+class Survey:
+    """Everything of a shot except the model: grid spacing, time step,
+    steps, source position and values, receivers, sponge, checkpoint
+    interval (0: library's choice)."""
+
+    def __init__(self, h, dt, nt, src, src_values, rec, sponge_width=0, sponge_alpha=0.0,
+                 every=0):
+        self.h = tuple(float(v) for v in h)
+        self.dt = float(dt)
+        self.nt = int(nt)
+        self.src = tuple(int(v) for v in src) if src is not None else None
+        self.src_values = src_values
+        self.rec = rec
+        self.sponge_width = int(sponge_width)
+        self.sponge_alpha = float(sponge_alpha)
+        self.every = int(every)
+
+
+class _TracesOfVelocity(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, v, survey):
+        nz, ny, nx = v.shape
+        dt = survey.dt
+        k = (v.detach().to(torch.float64) * dt).square().to(torch.float32)
+        prop = Propagator(nx, ny, nz, survey.h, k, src=survey.src, rec=survey.rec,
+                          sponge_width=survey.sponge_width, sponge_alpha=survey.sponge_alpha,
+                          device=v.device)
+        prop.record(survey.nt)
+        src = survey.src_values
+        if src is not None:
+            src = torch.as_tensor(src, dtype=torch.float32).to(v.device).contiguous()
+        prop.forward_checkpointed(survey.nt, src, survey.every)
+        ctx.prop = prop
+        ctx.dt = dt
+        ctx.save_for_backward(v)
+        return prop.traces[:, :prop.nrec].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        (v,) = ctx.saved_tensors
+        prop = ctx.prop
+        g = g.to(torch.float32).contiguous()
+        grad_k = prop.adjoint(g)
+        grad_v = grad_k * (2.0 * ctx.dt * ctx.dt) * v.detach().to(torch.float64)
+        prop.close()
+        ctx.prop = None
+        return grad_v.to(v.dtype), None
+
+
+def traces_of_velocity(v, survey: Survey):
+    """Receiver traces [nt][nrec] of the shot ``survey`` in the velocity
+    model ``v`` (dense [nz][ny][nx] device tensor), differentiable with
+    respect to ``v`` through the library's adjoint run (k = (v dt)^2)."""
+    return _TracesOfVelocity.apply(v, survey)

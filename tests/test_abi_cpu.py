@@ -111,3 +111,18 @@ def test_strerror_and_variants(w):
     assert names["auto"] == 0 and names["naive"] == 1
     assert len(names) == w.wave_variant_count() >= 3
     assert w.wave_variant_name(w.wave_variant_count()) is None
+
+
+def test_gradient_calls_reject_null_context(w):
+    lib = w.lib()
+    assert lib.wave_forward_checkpointed(None, 10, None, 0) == w.WAVE_EINVAL
+    assert lib.wave_adjoint(None, None, None, 0) == w.WAVE_EINVAL
+    assert lib.wave_grad_info(None, None, None, None, None) == w.WAVE_EINVAL
+
+
+def test_misfit_rejects_bad_arguments(w):
+    lib = w.lib()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: rejected before any launch
+    assert lib.wave_misfit(dummy, dummy, -1, None, dummy, None) == w.WAVE_EINVAL
+    assert lib.wave_misfit(dummy, dummy, 4, None, None, None) == w.WAVE_EINVAL
+    assert lib.wave_misfit(None, dummy, 4, None, dummy, None) == w.WAVE_EINVAL

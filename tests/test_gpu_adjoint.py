@@ -1,0 +1,244 @@
+"""Gradient with respect to k on the GPU (checkpointed forward run, adjoint
+run, FP64 accumulation), against the FP64 oracle's discrete adjoint.
+
+Exact checks:
+  - the checkpointed forward run leaves fields and traces bit for bit as a
+    plain run does (same kernels, same arithmetic);
+  - the gradient does not depend, bit for bit, on the checkpoint interval
+    (recomputed levels equal the first run's) nor on the tile shape (every
+    cell's arithmetic and the order of the sum over steps are fixed);
+  - the misfit residual is traces - observed exactly, the FP64 misfit is
+    the FP64 sum of its squares up to summation order.
+Accuracy against the oracle (relative L2 of the gradient):
+  - a ragged 37 x 21 x 19 grid with sponge, seeded random trace
+    derivatives, segments of 7 steps (partial last segment);
+  - the 48^3 crop of the gradient workload: misfit gradient end to end
+    (each side computes its own traces, residual and adjoint).
+The autograd wrapper is checked against a central difference of the GPU
+misfit along a smooth direction."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2204_03775_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+# FP32 adjoint against the FP64 oracle: the adjoint field carries about the
+# forward run's relative error (1e-6 .. 1e-5 after a few hundred steps, the
+# same recursion run backwards), and the gradient sums products of it with
+# FP32 Laplacians of the forward levels; 1e-4 leaves a decade of margin.
+BOUND_ADJOINT = 1e-4
+# end to end on the crop the residual is the small difference of two runs
+# (a 5 % anomaly), which scales the forward error up by about |d| / |r|
+BOUND_CROP = 1e-3
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def make_prop(wave, p, variant=0):
+    prop = wave.Propagator(p.nx, p.ny, p.nz, p.h, p.k32(), src=p.src, rec=p.rec,
+                           sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+    prop.configure(variant)
+    prop.record(p.nt)
+    return prop
+
+
+def src_of(p):
+    return torch.tensor(p.s, dtype=torch.float32, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    return inputs.random_problem(37, 21, 19, 40, seed=31, sponge_width=4, sponge_alpha=0.05,
+                                 nrec=24)
+
+
+@pytest.fixture(scope="module")
+def ragged_tg(ragged):
+    rng = np.random.default_rng(2208)
+    return rng.standard_normal((ragged.nt, len(ragged.rec)))
+
+
+def gpu_gradient(wave, p, tg, every, variant=0):
+    prop = make_prop(wave, p, variant)
+    prop.forward_checkpointed(p.nt, src_of(p), every)
+    g = prop.adjoint(torch.tensor(tg, dtype=torch.float32, device="cuda"))
+    prop.sync()
+    out = g.cpu().numpy()
+    info = prop.grad_info()
+    prop.close()
+    return out, info
+
+
+def test_checkpointed_forward_equals_plain_run(wave_mod, ragged):
+    p = ragged
+    a = make_prop(wave_mod, p)
+    a.run(p.nt, src_of(p))
+    b = make_prop(wave_mod, p)
+    b.forward_checkpointed(p.nt, src_of(p), 7)
+    for prop in (a, b):
+        prop.sync()
+    fa, fb = a.fields(), b.fields()
+    assert fa[2] == fb[2] == p.nt
+    for i in range(2):
+        assert torch.equal(a.interior(fa[i]), b.interior(fb[i]))
+    assert torch.equal(a.traces, b.traces)
+    assert b.grad_info()[:3] == (p.nt, 7, 6)
+    a.close()
+    b.close()
+
+
+def test_adjoint_matches_oracle(wave_mod, oracle_lib, ragged, ragged_tg):
+    p = ragged
+    print(f"case: adjoint {p.name} x {p.nt}, segments of 7", flush=True)
+    got, _ = gpu_gradient(wave_mod, p, ragged_tg, 7)
+    ref = oracle_lib.adjoint(p.k64(), p.h, p.nt, ragged_tg, s=p.s, src=p.src, rec=p.rec,
+                             sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+    e = rel(got, ref)
+    print(f"rel-L2 gradient {e:.3e}")
+    assert np.isfinite(got).all() and np.abs(ref).max() > 0
+    assert e <= BOUND_ADJOINT
+
+
+def test_gradient_independent_of_checkpoint_interval(wave_mod, ragged, ragged_tg):
+    p = ragged
+    ref, _ = gpu_gradient(wave_mod, p, ragged_tg, 7)
+    for every in (1, 3, 40, 100, 0):
+        print(f"case: adjoint {p.name}, every {every}", flush=True)
+        got, info = gpu_gradient(wave_mod, p, ragged_tg, every)
+        assert np.array_equal(got, ref), every
+        if every == 0:
+            assert info[1] == p.nt  # a small run keeps every level
+
+
+def test_gradient_independent_of_tiling(wave_mod, ragged, ragged_tg):
+    p = ragged
+    ref, _ = gpu_gradient(wave_mod, p, ragged_tg, 9)
+    for v in range(1, wave_mod.wave_variant_count()):
+        print(f"case: adjoint {p.name}, variant {wave_mod.wave_variant_name(v)}", flush=True)
+        got, _ = gpu_gradient(wave_mod, p, ragged_tg, 9, variant=v)
+        assert np.array_equal(got, ref), v
+
+
+def test_adjoint_accumulates_and_repeats(wave_mod, ragged, ragged_tg):
+    p = ragged
+    prop = make_prop(wave_mod, p)
+    prop.forward_checkpointed(p.nt, src_of(p), 6)
+    tg = torch.tensor(ragged_tg, dtype=torch.float32, device="cuda")
+    g1 = prop.adjoint(tg).clone()
+    g2 = prop.adjoint(tg)            # levels recomputed from checkpoints
+    prop.adjoint(tg, grad=g2, accumulate=True)
+    prop.sync()
+    assert torch.equal(g2, 2 * g1)
+    prop.close()
+
+
+def test_no_receivers_no_gradient(wave_mod, ragged):
+    p = ragged
+    prop = wave_mod.Propagator(p.nx, p.ny, p.nz, p.h, p.k32(), src=p.src,
+                               sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+    prop.forward_checkpointed(p.nt, src_of(p), 5)
+    g = prop.adjoint()
+    prop.sync()
+    assert torch.count_nonzero(g).item() == 0
+    prop.close()
+
+
+def test_misfit_reduction(wave_mod):
+    rng = np.random.default_rng(5)
+    for n in (1, 1000, 123457):
+        a = torch.tensor(rng.standard_normal(n), dtype=torch.float32, device="cuda")
+        b = torch.tensor(rng.standard_normal(n), dtype=torch.float32, device="cuda")
+        J, r = wave_mod.misfit(a, b)
+        torch.cuda.synchronize()
+        assert torch.equal(r, a - b)
+        ref = 0.5 * np.sum((a.cpu().numpy().astype(np.float64) - b.cpu().numpy()) ** 2)
+        assert abs(J.item() - ref) <= 1e-12 * ref
+
+
+def test_error_paths(wave_mod, ragged):
+    p = ragged
+    prop = make_prop(wave_mod, p)
+    with pytest.raises(wave_mod.WaveError) as e:
+        prop.adjoint(torch.zeros((p.nt, len(p.rec)), dtype=torch.float32, device="cuda"))
+    assert e.value.code == wave_mod.WAVE_ESTATE
+    with pytest.raises(wave_mod.WaveError) as e:
+        prop.forward_checkpointed(p.nt + 1, src_of(p).repeat(2), 5)  # beyond the trace buffer
+    assert e.value.code == wave_mod.WAVE_EINVAL
+    prop.close()
+    half = wave_mod.Propagator(p.nx, p.ny, p.nz, p.h, p.k32(), src=p.src, dtype="f16")
+    with pytest.raises(wave_mod.WaveError) as e:
+        half.forward_checkpointed(p.nt, src_of(p), 5)
+    assert e.value.code == wave_mod.WAVE_EINVAL
+    half.close()
+
+
+@pytest.fixture(scope="module")
+def crop():
+    return inputs.gradient_crop()
+
+
+def test_crop_misfit_gradient(wave_mod, oracle_lib, crop):
+    p, q = crop.shot, crop.observed()
+    print(f"case: misfit gradient {p.name} {p.shape} x {p.nt}", flush=True)
+    obs = make_prop(wave_mod, q)
+    obs.run(q.nt, src_of(q))
+    prop = make_prop(wave_mod, p)
+    prop.forward_checkpointed(p.nt, src_of(p), crop.every)
+    J, res = wave_mod.misfit(prop.traces[:, :prop.nrec].contiguous(),
+                             obs.traces[:, :obs.nrec].contiguous())
+    g = prop.adjoint(res)
+    prop.sync()
+    got = g.cpu().numpy()
+
+    _, _, tr = oracle_lib.run(p.k64(), p.h, p.nt, s=p.s, src=p.src, rec=p.rec,
+                              sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+    _, _, tr_obs = oracle_lib.run(q.k64(), q.h, q.nt, s=q.s, src=q.src, rec=q.rec,
+                                  sponge_width=q.sponge_width, sponge_alpha=q.sponge_alpha)
+    r = tr - tr_obs
+    ref = oracle_lib.adjoint(p.k64(), p.h, p.nt, r, s=p.s, src=p.src, rec=p.rec,
+                             sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+    J_ref = 0.5 * float(np.sum(r * r))
+    e_g, e_J = rel(got, ref), abs(J.item() - J_ref) / J_ref
+    print(f"misfit {J.item():.6e} (oracle {J_ref:.6e}, rel {e_J:.2e}); gradient rel-L2 {e_g:.3e}")
+    assert e_J <= BOUND_CROP and e_g <= BOUND_CROP
+    obs.close()
+    prop.close()
+
+
+def test_autograd_directional_derivative(wave_mod, crop):
+    p, q = crop.shot, crop.observed()
+    obs = make_prop(wave_mod, q)
+    obs.run(q.nt, src_of(q))
+    obs.sync()
+    d_obs = obs.traces[:, :obs.nrec].clone()
+    obs.close()
+    survey = wave_mod.Survey(p.h, p.dt, p.nt, p.src, p.s, p.rec, p.sponge_width, p.sponge_alpha,
+                             every=crop.every)
+    v = torch.tensor(p.v, dtype=torch.float32, device="cuda", requires_grad=True)
+
+    def J_of(vv):
+        tr = wave_mod.traces_of_velocity(vv, survey)
+        return 0.5 * ((tr.double() - d_obs.double()) ** 2).sum()
+
+    J = J_of(v)
+    J.backward()
+    gv = v.grad.double()
+    # smooth direction: a Gaussian bump of 20 m/s at the anomaly
+    m = p.nx
+    z, y, x = np.ogrid[:m, :m, :m]
+    c = crop.anomaly
+    d = 20.0 * np.exp(-((z - c[0]) ** 2 + (y - c[1]) ** 2 + (x - c[2]) ** 2) / (2 * 6.0 ** 2))
+    dt = torch.tensor(d, dtype=torch.float64, device="cuda")
+    with torch.no_grad():
+        jp = J_of((v.double() + dt).float()).item()
+        jm = J_of((v.double() - dt).float()).item()
+    fd = (jp - jm) / 2.0
+    an = float((gv * dt).sum().item())
+    print(f"J {J.item():.6e}; directional derivative: adjoint {an:.6e}, central difference {fd:.6e}")
+    assert abs(an - fd) <= 1e-2 * abs(fd)
