@@ -53,7 +53,9 @@ WORKLOADS = {
                     "centre, 16 random receivers, zero ghost layer (synthetic, seeded)",
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_large_shot.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2204_03775_amd", "csrc", "wave.hip")
+# the sources of the FP32 step kernel (types, device code, instantiation)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2204_03775_amd", "csrc", f)
+                  for f in ("wave_dev.h", "wave_step.h", "k_fwd_f32.hip")]
 
 
 def log(*a):
@@ -61,8 +63,11 @@ def log(*a):
 
 
 def source_digest() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel_name: str, zchunk: int):

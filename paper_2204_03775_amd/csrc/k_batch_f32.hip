@@ -1,0 +1,12 @@
+// F32-storage batched (persistent, many shots per launch) step kernels, one
+// per tile shape.
+#include "wave_step.h"
+
+namespace wavek {
+
+#define INST(TXV, TY, RY) \
+    template __global__ void step_batch<WAVE_F32, TXV, TY, RY>(const ShotDesc *__restrict__, BatchItems, int);
+WAVE_TILE_SHAPES(INST)
+#undef INST
+
+}  // namespace wavek

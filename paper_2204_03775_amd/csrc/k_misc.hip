@@ -1,0 +1,117 @@
+// Kernels outside the time step: the k range check at set-up, batch
+// counter clearing, and the adjoint run's receiver injection, misfit
+// reduction and gradient output.
+
+#include "wave_dev.h"
+
+namespace wavek {
+
+// Adds k * trace_grad[row][r] at the receiver cells: one thread per distinct
+// cell, summing its receivers in a fixed order (deterministic, no atomics).
+__global__ void inject_receivers(float *phi, const float *__restrict__ k, const long long *__restrict__ cell_off,
+                                 const int *__restrict__ cell_start, const int *__restrict__ cell_rec,
+                                 int ncells, const float *__restrict__ tg_row)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncells) {
+        float s = 0.f;
+        for (int i = cell_start[c]; i < cell_start[c + 1]; ++i)
+            s += tg_row[cell_rec[i]];
+        const long long o = cell_off[c];
+        phi[o] = fmaf(k[o], s, phi[o]);
+    }
+}
+
+// misfit = 0.5 sum (traces - d_obs)^2 in FP64 (one work-group, fixed
+// summation order, differences taken exactly); residual = traces - d_obs
+// rounded to FP32 when requested.
+__global__ __launch_bounds__(1024) void misfit_kernel(const float *__restrict__ tr,
+                                                      const float *__restrict__ obs, long long n,
+                                                      float *residual, double *out)
+{
+    __shared__ double part[1024];
+    double acc = 0.0;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+        const double r = (double)tr[i] - (double)obs[i];  // exact
+        if (residual)
+            residual[i] = (float)r;  // == the FP32 difference
+        acc += r * r;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        *out = 0.5 * part[0];
+}
+
+// dense[z][y][x] (+)= acc at the interior cells of the field layout.
+__global__ __launch_bounds__(256) void grad_to_dense(const double *__restrict__ acc, double *dense, int nx,
+                                                    int ny, int nz, int px, int x0, long long plane,
+                                                    int accumulate)
+{
+    const long long n = (long long)nx * ny * nz;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx);
+        const int y = (int)((i / nx) % ny);
+        const int z = (int)(i / ((long long)nx * ny));
+        const double v = acc[(long long)(z + kGhost) * plane + (long long)(y + kGhost) * px + x0 + x];
+        dense[i] = accumulate ? dense[i] + v : v;
+    }
+}
+
+// Clears both ticket sets at the start of a batched run (a kernel rather
+// than a memset, so that it can sit in a captured graph).
+__global__ void clear_counters(int *c)
+{
+    if (threadIdx.x < 16)
+        c[threadIdx.x] = 0;
+}
+
+// Max, min and a non-finite flag of an FP32 k over the interior, as float
+// bit patterns (valid for non-negative values; negatives raise the flag).
+__global__ __launch_bounds__(256) void k_range(const float *__restrict__ k, int nx, int ny, int nz,
+                                               int px, int x0, long long plane, unsigned *out)
+{
+    __shared__ unsigned smax[256], smin[256], sbad[256];
+    unsigned mx = 0u, mn = 0x7f800000u, bad = 0u;
+    const long long n = (long long)nx * ny * nz;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx);
+        const int y = (int)((i / nx) % ny);
+        const int z = (int)(i / ((long long)nx * ny));
+        const float v = k[(long long)(z + kGhost) * plane + (long long)(y + kGhost) * px + x0 + x];
+        if (!(v >= 0.f) || !(v < INFINITY)) {
+            bad = 1u;
+        } else {
+            const unsigned b = __float_as_uint(v);
+            mx = max(mx, b);
+            mn = min(mn, b);
+        }
+    }
+    const int t = threadIdx.x;
+    smax[t] = mx;
+    smin[t] = mn;
+    sbad[t] = bad;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) {
+            smax[t] = max(smax[t], smax[t + s]);
+            smin[t] = min(smin[t], smin[t + s]);
+            sbad[t] |= sbad[t + s];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        atomicMax(&out[0], smax[0]);
+        atomicMin(&out[1], smin[0]);
+        atomicOr(&out[2], sbad[0]);
+    }
+}
+
+}  // namespace wavek

@@ -1,41 +1,6 @@
-// libwave.so: time stepping of the 3-D acoustic wave equation with the
-// 25-point, 8th-order Laplacian inside a leapfrog update (paper Section III:
-// Eq. 2, the Laplacian and Algorithm 1), written for MI355X (gfx950, CDNA4,
-// wave64).  The C ABI is declared in include/wave.h.
-//
-// Kernel design.  The paper maps X and Y onto its processor grid and keeps
-// the whole Z column in each processor's memory (Section IV-B); a GPU has a
-// memory hierarchy instead, so the mapping here is the usual 2.5-D one:
-//   - a work-group owns an x-y tile and a range of z planes and marches
-//     through them;
-//   - each thread owns 4 consecutive x cells in RY rows and keeps its z
-//     column z-4 .. z+4 in a register queue (the GPU counterpart of the
-//     paper's z update from local memory, Section IV-C);
-//   - the centre plane of the tile, with a 4-cell halo in x and y, is
-//     staged in LDS (double buffered: one barrier per plane) and the x and
-//     y taps are read from there;
-//   - the next plane, the halo and u^{n-1}, k are prefetched one plane
-//     ahead so that HBM reads overlap the arithmetic;
-//   - sponge, source injection and receiver sampling are fused: the
-//     update, the source add and a per-work-group receiver epilogue happen
-//     in the same launch.
-// The step is bound by HBM bandwidth (about 3 flop per byte against a ridge
-// near 20 for FP32 vector math), so nothing here uses the matrix cores.
-//
-// Laplacian form.  With FP32 fields the Laplacian is evaluated as
-//   sum_a sum_m (c_m / h_a^2) (u(+m e_a) + u(-m e_a) - 2 u),
-// which equals the paper's form because c_0 = -2 sum c_m, and which maps a
-// constant to exactly zero whatever the rounding of the FP32 weights.  The
-// classic form c_0 u + sum c_m (...) with FP32-rounded weights does not,
-// and the small spurious mass term it leaves shifts the phase by about
-// 2e-5 over five wavelengths at 17 cells per wavelength.  16-bit storage
-// rounds each stored value far more coarsely than that, so those kernels
-// keep the classic form and its 12 fewer operations per cell.
-//
-// Storage.  Fields are FP32, or FP16 / BF16 with FP32 arithmetic: a 16-bit
-// field holds x * 2^-e for one exponent e per time level, chosen on the
-// device when the level is written so that the largest value stays below
-// 2^14 (see step_scales).  Decoding multiplies by 2^e, which is exact.
+// libwave.so host side: contexts, launch planning, the checkpointed
+// gradient driver, batched runs and the C ABI of include/wave.h.  The
+// kernels live in wave_step.h (instantiated by the k_*.hip units).
 
 #include <hip/hip_runtime.h>
 
@@ -46,980 +11,15 @@
 #include <cstring>
 #include <new>
 #include <string>
-#include <type_traits>
 #include <utility>
 #include <vector>
 
 #include "wave.h"
+#include "wave_dev.h"
+
+using namespace wavek;
 
 namespace {
-
-constexpr int kGhost = 4;
-constexpr int kRowAlignBytes = 128;  // interior rows start on this boundary
-
-// 8th-order central second-derivative weights (four points each way).
-constexpr double kC0 = -205.0 / 72.0;
-constexpr double kCm[4] = {8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
-// max over wavenumbers of |c0 + 2 sum c_m cos(m kh)|, reached at kh = pi;
-// it also equals |c0| + 2 sum |c_m|, which bounds |lap u| by this times
-// max|u| sum 1/h^2.
-constexpr double kSymbolMax = 2048.0 / 315.0;
-
-// largest scaled magnitude a 16-bit field is written with (2^14)
-constexpr int kScaledTopExp = 14;
-
-constexpr int elem_bytes(int dtype) { return dtype == WAVE_F32 ? 4 : 2; }
-
-struct alignas(16) f4 {
-    float v[4];
-};
-
-struct Coefs {
-    float ctr;    // c0 * (1/dx^2 + 1/dy^2 + 1/dz^2): the centre counted once
-    float cx[4];  // c_m / dx^2
-    float cy[4];
-    float cz[4];
-};
-
-struct StepArgs {
-    const void *k;
-    const void *cur;
-    void *nxt;  // u^{n-1} (adjoint: phi^{m+2}; imaging: phi^m)
-    const float *__restrict__ gx;
-    const float *__restrict__ gy;
-    const float *__restrict__ gz;
-    Coefs c;
-    int nx, ny, nz;
-    int px;             // row pitch in elements
-    int x0;             // element offset of interior x = 0 in a row
-    long long plane;    // elements per plane
-    int nxq;            // ceil(nx / 4): 4-cell columns holding interior cells
-    int ntx, nty, nchunks, zc, nwg;
-    int src_z, src_y, src_x;  // src_z < 0: no source
-    const float *src_ptr;     // device value of this step, or NULL
-    float src_val;            // used when src_ptr is NULL
-    const int *rec_start;     // [nwg + 1] receiver ranges per work-group
-    const long long *rec_off; // element offset of each receiver
-    const int *rec_idx;       // receiver number
-    float *trace_row;         // row of this step, or NULL
-    // 16-bit storage only
-    int step;                 // n: this launch writes u^{n+1}
-    float k_scale;            // k = stored k * k_scale
-    int *exps;                // [4] exponent of u^m in slot m & 3
-    unsigned *maxes;          // [4] max |u^m| (float bits) in slot m & 3
-    // output field: == nxt for the in-place step (each cell is read, then
-    // written, by the same thread), a separate level otherwise
-    void *out;
-    // imaging only: FP64 accumulator in the field layout (8-byte cells)
-    double *grad;
-};
-
-// What a tiled launch computes (FP32 storage only for the last two):
-//   kFwd  u^{n+1} = G (2 u^n - G u^{n-1} + k lap u^n) (+ source, receivers);
-//   kAdj  the adjoint step phi^m = 2 psi + k lap psi - G^2 phi^{m+2} with
-//         psi = G phi^{m+1} (G applied to every loaded value);
-//   kImg  grad += (phi / k) G lap a: the imaging term of one adjoint step.
-constexpr int kFwd = 0;
-constexpr int kAdj = 1;
-constexpr int kImg = 2;
-
-__device__ __forceinline__ float src_value(const StepArgs &a)
-{
-    return a.src_ptr ? a.src_ptr[0] : a.src_val;
-}
-
-// Work-groups are handed to the 8 XCDs round-robin by block index; map
-// block b to logical work-group (b % 8) * (G / 8) + b / 8 so that each XCD
-// gets a contiguous run of neighbouring tiles whose halos share its L2.
-__device__ __forceinline__ int logical_wg()
-{
-    const int b = blockIdx.x;
-    const int per = gridDim.x >> 3;
-    return (b & 7) * per + (b >> 3);
-}
-
-// ---------------------------------------------------------------------------
-// storage formats
-
-template <int KIND>
-struct Store;
-template <>
-struct Store<WAVE_F32> {
-    static constexpr bool scaled = false;
-    static constexpr unsigned bytes = 4;
-};
-template <>
-struct Store<WAVE_F16> {
-    static constexpr bool scaled = true;
-    static constexpr unsigned bytes = 2;
-    static __device__ __forceinline__ float dec(unsigned bits)
-    {
-        return (float)__builtin_bit_cast(_Float16, (unsigned short)bits);
-    }
-    static __device__ __forceinline__ unsigned enc(float x)
-    {
-        return __builtin_bit_cast(unsigned short, (_Float16)x);
-    }
-};
-template <>
-struct Store<WAVE_BF16> {
-    static constexpr bool scaled = true;
-    static constexpr unsigned bytes = 2;
-    static __device__ __forceinline__ float dec(unsigned bits) { return __uint_as_float(bits << 16); }
-    static __device__ __forceinline__ unsigned enc(float x)
-    {
-        return __builtin_bit_cast(unsigned short, (__bf16)x);
-    }
-};
-
-// Raw buffer access.  A buffer resource covers one plane of one field; any
-// byte offset at or past its size reads as zero and drops stores, which is
-// how out-of-range tile cells are masked without branches.
-typedef unsigned u4raw __attribute__((vector_size(16)));
-typedef unsigned u2raw __attribute__((vector_size(8)));
-constexpr int kRsrcWord3 = 0x00020000;  // 32-bit data format, raw (stride 0) access
-constexpr unsigned kOff = 0xffffffffu;  // an offset outside every resource
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *field, long long plane_bytes,
-                                                            int z)
-{
-    const char *p = reinterpret_cast<const char *>(field) + (long long)(z + kGhost) * plane_bytes;
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), (short)0, (int)plane_bytes,
-                                             kRsrcWord3);
-}
-
-// Cache policy of a buffer access (gfx950 encoding of the aux operand):
-// bit 1 = non-temporal.  u^{n-1} and k are read exactly once per step and
-// u^{n+1} is not read again in the step, so they are streamed
-// non-temporally; u^n is read by the neighbouring tiles as their halo and
-// keeps the default policy, so it stays resident in L2.
-constexpr int kKeep = 0;
-constexpr int kStream = 2;
-
-// Four consecutive cells, decoded to FP32 (times `scale` for 16-bit data).
-template <int KIND, int POL>
-__device__ __forceinline__ f4 load4(__amdgpu_buffer_rsrc_t r, unsigned off, float scale)
-{
-    f4 o;
-    if constexpr (KIND == WAVE_F32) {
-        const u4raw v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, POL);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            o.v[e] = __uint_as_float(v[e]);
-    } else {
-        const u2raw v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, POL);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            o.v[e] = Store<KIND>::dec((v[e >> 1] >> (16 * (e & 1))) & 0xffffu) * scale;
-    }
-    return o;
-}
-
-template <int KIND>
-__device__ __forceinline__ void store4(__amdgpu_buffer_rsrc_t r, unsigned off, const f4 &v, float inv)
-{
-    if constexpr (KIND == WAVE_F32) {
-        u4raw w;
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            w[e] = __float_as_uint(v.v[e]);
-        __builtin_amdgcn_raw_buffer_store_b128(w, r, off, 0, kStream);
-    } else {
-        u2raw w;
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-            w[h] = Store<KIND>::enc(v.v[2 * h] * inv) | (Store<KIND>::enc(v.v[2 * h + 1] * inv) << 16);
-        __builtin_amdgcn_raw_buffer_store_b64(w, r, off, 0, kStream);
-    }
-}
-
-template <int KIND>
-__device__ __forceinline__ void store1(__amdgpu_buffer_rsrc_t r, unsigned off, float v, float inv)
-{
-    if constexpr (KIND == WAVE_F32)
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, kStream);
-    else
-        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)Store<KIND>::enc(v * inv), r, off, 0,
-                                              kStream);
-}
-
-// Element read outside the hot loop (receivers, exports).
-template <int KIND>
-__device__ __forceinline__ float read_elem(const void *f, long long i, float scale)
-{
-    if constexpr (KIND == WAVE_F32)
-        return static_cast<const float *>(f)[i];
-    else
-        return Store<KIND>::dec(static_cast<const unsigned short *>(f)[i]) * scale;
-}
-
-// Scales of one step with 16-bit storage.  u^{n+1} is bounded by
-// 7 max(|u^n|, |u^{n-1}|) + |s_n| (2 + 1 from the time levels, 4 from
-// k |lap| under the stability limit, G <= 1); its exponent is chosen so
-// that 8 M + |s_n| < 2^(e + 14), which leaves a factor 4 below the FP16
-// maximum.  All work-groups compute the same value from the same inputs.
-struct Scales {
-    float cur, prev, out_inv, out;
-    int e_out;
-};
-
-// The same step in the stored (scaled) units.  With U, P, K the decoded
-// but unscaled u^n, u^{n-1}, k and every scale a power of two, the stored
-// u^{n+1} is
-//   O = g (fma(K, LAP_C(U), 2A U) - g B P),
-//   A = sc_cur / sc_out, B = sc_prev / sc_out, C = k_scale * A,
-// with LAP_C the Laplacian whose weights are multiplied by C.  Scaling by
-// a power of two commutes with every FP32 rounding, so this is bit for bit
-// the decode -> compute -> encode sequence, without the per-value
-// multiplies.
-struct Folded {
-    Coefs c;       // weights times C
-    float two_a;   // 2 A
-    float b;       // B
-};
-
-__device__ __forceinline__ Folded fold_scales(const Coefs &c, const Scales &sc, float k_scale)
-{
-    Folded f;
-    const float A = sc.cur * sc.out_inv;
-    const float C = k_scale * A;
-    f.c.ctr = c.ctr * C;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        f.c.cx[m] = c.cx[m] * C;
-        f.c.cy[m] = c.cy[m] * C;
-        f.c.cz[m] = c.cz[m] * C;
-    }
-    f.two_a = 2.f * A;
-    f.b = sc.prev * sc.out_inv;
-    return f;
-}
-
-__device__ __forceinline__ Scales step_scales(const StepArgs &a)
-{
-    const int n = a.step;
-    const float m = fmaxf(__uint_as_float(a.maxes[n & 3]), __uint_as_float(a.maxes[(n + 3) & 3]));
-    const float s = a.src_z >= 0 ? fabsf(src_value(a)) : 0.f;
-    const float bound = 8.f * m + s;
-    int e = 0;
-    if (bound > 0.f && bound < INFINITY) {
-        int ex;
-        (void)frexpf(bound, &ex);  // bound < 2^ex
-        e = min(max(ex - kScaledTopExp, -110), 110);
-    }
-    Scales sc;
-    sc.cur = ldexpf(1.f, a.exps[n & 3]);
-    sc.prev = ldexpf(1.f, a.exps[(n + 3) & 3]);
-    sc.out = ldexpf(1.f, e);
-    sc.out_inv = ldexpf(1.f, -e);
-    sc.e_out = e;
-    return sc;
-}
-
-// Publish this step's exponent and clear the max slot the next step fills
-// after this one (slot n + 2, which no launch of this step reads).
-__device__ __forceinline__ void publish_scale(const StepArgs &a, const Scales &sc, int lid, int tid)
-{
-    if (lid == 0 && tid == 0) {
-        a.exps[(a.step + 1) & 3] = sc.e_out;
-        a.maxes[(a.step + 2) & 3] = 0u;
-    }
-}
-
-// Fold a per-thread max |u^{n+1}| into the step's slot: a reduction across
-// the wave, then one atomic per wave (on the float bit pattern, valid for
-// non-negative values).
-__device__ __forceinline__ void fold_max(const StepArgs &a, float m)
-{
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1)
-        m = fmaxf(m, __shfl_xor(m, d));
-    if ((threadIdx.x & 63) == 0)
-        atomicMax(&a.maxes[(a.step + 1) & 3], __float_as_uint(m));
-}
-
-// Receiver epilogue: after the whole tile column is written, copy the
-// receivers this work-group owns into the trace row.
-template <int KIND>
-__device__ __forceinline__ void sample_receivers(const StepArgs &a, int lid, int tid, int nt,
-                                                 float scale)
-{
-    if (!a.trace_row)
-        return;
-    const int r0 = a.rec_start[lid], r1 = a.rec_start[lid + 1];
-    if (r0 == r1)
-        return;
-    __syncthreads();
-    for (int i = r0 + tid; i < r1; i += nt)
-        a.trace_row[a.rec_idx[i]] = read_elem<KIND>(a.out, a.rec_off[i], scale);
-}
-
-// Calls f(integral_constant<int, S>) for S = B, B+1, ... < E while f
-// returns true: a loop unrolled at compile time, so every index that
-// depends on S is a constant and register arrays stay in registers.
-template <int B, int E, class F>
-__device__ __forceinline__ void static_for_while(F &&f)
-{
-    if constexpr (B < E) {
-        if (f(std::integral_constant<int, B>{}))
-            static_for_while<B + 1, E>(f);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// the step
-
-// One work-group's share of a step: the tile and z-chunk numbered `lid`
-// (tiles x fastest, then y, then chunks) of the grid described by `a`.
-template <int KIND, int TXV, int TY, int RY, int MODE = kFwd>
-__device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
-{
-    constexpr int NT = TXV * TY;
-    constexpr int TYR = TY * RY;             // tile rows
-    constexpr int LW = TXV + 2;              // float4 per LDS row: one halo float4 each side
-    constexpr int LH = TYR + 8;              // LDS rows: 4 halo rows each side
-    constexpr int NH = 8 * TXV + 2 * TYR;    // halo float4 per plane
-    constexpr int HPT = (NH + NT - 1) / NT;  // halo float4 per thread
-    constexpr int QS = 10;                   // queue slots: 9 live planes + 1 being filled
-    constexpr unsigned EB = Store<KIND>::bytes;
-    constexpr bool SCALED = Store<KIND>::scaled;
-    constexpr bool ADJ = MODE == kAdj, IMG = MODE == kImg;
-    static_assert(MODE == kFwd || KIND == WAVE_F32, "adjoint and imaging steps are FP32 only");
-    __shared__ f4 lds[2][LH][LW];
-
-    const int tx = lid % a.ntx;
-    const int rest = lid / a.ntx;
-    const int ty = rest % a.nty;
-    const int ch = rest / a.nty;
-    const int z0 = ch * a.zc;
-    const int z1 = min(z0 + a.zc, a.nz);
-
-    const int tid = threadIdx.x;
-    const int lx = tid % TXV;
-    const int ly = tid / TXV;
-    const int xq0 = tx * TXV;          // first 4-cell column of the tile
-    const int y0 = ty * TYR;           // first row of the tile
-    const int xq = xq0 + lx;           // this thread's 4-cell column
-    const int x = 4 * xq;
-
-    Scales sc{1.f, 1.f, 1.f, 1.f, 0};
-    Folded fd{a.c, 2.f, 1.f};
-    if constexpr (SCALED) {
-        sc = step_scales(a);
-        publish_scale(a, sc, lid, tid);
-        fd = fold_scales(a.c, sc, a.k_scale);
-    }
-
-    // A 4-cell column may be read when it lies in [-1, nxq]: allocated and
-    // either interior, ghost or (beyond nx + 3) never used by an interior cell.
-    const bool col_load = xq <= a.nxq;
-    const bool col_interior = x < a.nx;
-    const bool col_full = x + 3 < a.nx;
-
-    // own rows: byte offsets within a plane (kOff when masked)
-    int row[RY];
-    bool row_int[RY];
-    unsigned own_ld[RY], own_in[RY];
-#pragma unroll
-    for (int r = 0; r < RY; ++r) {
-        row[r] = y0 + ly * RY + r;
-        row_int[r] = col_interior && row[r] < a.ny;
-        const unsigned b = EB * unsigned((row[r] + kGhost) * a.px + a.x0 + x);
-        own_ld[r] = (col_load && row[r] < a.ny + kGhost) ? b : kOff;
-        own_in[r] = row_int[r] ? b : kOff;
-    }
-
-    // halo items of this thread
-    unsigned h_b[HPT];
-    int h_lds[HPT];  // flat LDS index (row * LW + col), -1 when unused
-#pragma unroll
-    for (int h = 0; h < HPT; ++h) {
-        const int i = tid + h * NT;
-        int hr, hc;
-        if (i < 8 * TXV) {
-            const int band = i / TXV;
-            hr = band < 4 ? band - 4 : TYR + band - 4;
-            hc = i % TXV;
-        } else {
-            const int j = i - 8 * TXV;
-            hr = j % TYR;
-            hc = (j / TYR) ? TXV : -1;
-        }
-        const bool use = i < NH;
-        h_lds[h] = use ? (hr + 4) * LW + (hc + 1) : -1;
-        const int gy = y0 + hr;
-        const int gq = xq0 + hc;
-        const bool ok = use && gy >= -kGhost && gy < a.ny + kGhost && gq >= -1 && gq <= a.nxq;
-        h_b[h] = ok ? EB * unsigned((gy + kGhost) * a.px + a.x0 + 4 * gq) : kOff;
-    }
-    // adjoint: sponge factor g_x g_y of every cell this thread loads
-    // (cells outside the interior hold zeros; their factor is irrelevant)
-    f4 gh[ADJ ? HPT : 1];
-    if constexpr (ADJ) {
-#pragma unroll
-        for (int h = 0; h < HPT; ++h) {
-            const int i = tid + h * NT;
-            int hr, hc;
-            if (i < 8 * TXV) {
-                const int band = i / TXV;
-                hr = band < 4 ? band - 4 : TYR + band - 4;
-                hc = i % TXV;
-            } else {
-                const int j = i - 8 * TXV;
-                hr = j % TYR;
-                hc = (j / TYR) ? TXV : -1;
-            }
-            const int gy = y0 + hr;
-            const float fy = (gy >= 0 && gy < a.ny) ? a.gy[gy] : 0.f;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int gxi = 4 * (xq0 + hc) + e;
-                gh[h].v[e] = (gxi >= 0 && gxi < a.nx) ? a.gx[gxi] * fy : 0.f;
-            }
-        }
-    }
-
-    // sponge factors that do not change along z
-    f4 gxv = {{1.f, 1.f, 1.f, 1.f}};
-    if (col_interior) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            gxv.v[e] = (x + e < a.nx) ? a.gx[x + e] : 1.f;
-    }
-    float gyv[RY];
-#pragma unroll
-    for (int r = 0; r < RY; ++r)
-        gyv[r] = row_int[r] ? a.gy[row[r]] : 1.f;
-    f4 gown[ADJ ? RY : 1];  // adjoint: g_x g_y of the own cells
-    if constexpr (ADJ) {
-#pragma unroll
-        for (int r = 0; r < RY; ++r)
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                gown[r].v[e] = gxv.v[e] * gyv[r];
-    }
-
-    // source ownership (the value is read once, before the march)
-    int src_r = -1, src_e = 0;
-    if (a.src_z >= z0 && a.src_z < z1 && (a.src_x >> 2) == xq) {
-#pragma unroll
-        for (int r = 0; r < RY; ++r)
-            if (row[r] == a.src_y)
-                src_r = r;
-        src_e = a.src_x & 3;
-    }
-    const float sval = src_r >= 0 ? src_value(a) * sc.out_inv : 0.f;
-
-    const long long pbytes = a.plane * (long long)EB;
-    const __amdgpu_buffer_rsrc_t gz_r = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float *>(a.gz), (short)0, a.nz * (int)sizeof(float), kRsrcWord3);
-
-    // register queue: at phase s the plane z - 4 + i lives in slot (s + i) % QS
-    auto gz_at = [&](int z) {  // g_z, zero outside the interior (reads nothing there)
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(gz_r, 4u * unsigned(z), 0, 0));
-    };
-    f4 q[QS][RY];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const __amdgpu_buffer_rsrc_t rc = plane_rsrc(a.cur, pbytes, z0 - 4 + i);
-#pragma unroll
-        for (int r = 0; r < RY; ++r)
-            q[i][r] = load4<KIND, kKeep>(rc, own_ld[r], 1.f);
-        if constexpr (ADJ) {
-            const float gzi = gz_at(z0 - 4 + i);
-#pragma unroll
-            for (int r = 0; r < RY; ++r)
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    q[i][r].v[e] *= gown[r].v[e] * gzi;
-        }
-    }
-
-    // values of the next plane, loaded one plane ahead into the set of the
-    // other parity (no copies, so no wait before the next loads are issued)
-    f4 pv[2][RY], kv[2][RY], hv[2][HPT];
-    float gzv[2], gzq[2];  // g_z of the plane and (adjoint) of the queue plane z + 4
-    auto prefetch = [&](int z, int slot, int set) {
-        const __amdgpu_buffer_rsrc_t rq = plane_rsrc(a.cur, pbytes, z + 4);
-        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(a.nxt, pbytes, z);
-        const __amdgpu_buffer_rsrc_t rk = plane_rsrc(a.k, pbytes, z);
-        const __amdgpu_buffer_rsrc_t rh = plane_rsrc(a.cur, pbytes, z);
-#pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            q[slot][r] = load4<KIND, kKeep>(rq, own_ld[r], 1.f);
-            pv[set][r] = load4<KIND, kStream>(rp, own_in[r], 1.f);
-            kv[set][r] = load4<KIND, kStream>(rk, own_in[r], 1.f);
-        }
-#pragma unroll
-        for (int h = 0; h < HPT; ++h)
-            hv[set][h] = load4<KIND, kKeep>(rh, h_b[h], 1.f);
-        gzv[set] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(gz_r, 4u * z, 0, 0));
-        if constexpr (ADJ)
-            gzq[set] = gz_at(z + 4);
-    };
-    prefetch(z0, 8, 0);
-
-    float tmax = 0.f;  // max |stored u^{n+1}| written by this thread (16-bit storage)
-    const Coefs c = fd.c;
-    for (int zb = z0; zb < z1; zb += QS) {
-        static_for_while<0, QS>([&](auto phase) __attribute__((always_inline)) -> bool {
-            constexpr int s = decltype(phase)::value;
-            const int z = zb + s;
-            if (z >= z1)
-                return false;
-            const int cur_set = s & 1;
-            // next plane (clamped on the last one, whose loads go unused)
-            prefetch(min(z + 1, z1 - 1), (s + 9) % QS, cur_set ^ 1);
-
-            if constexpr (ADJ) {
-                // psi = G phi: the plane that just entered the queue (z + 4)
-                // and this plane's halo
-#pragma unroll
-                for (int r = 0; r < RY; ++r)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        q[(s + 8) % QS][r].v[e] *= gown[r].v[e] * gzq[cur_set];
-#pragma unroll
-                for (int h = 0; h < HPT; ++h)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        hv[cur_set][h].v[e] *= gh[h].v[e] * gzv[cur_set];
-            }
-            const int b = z & 1;
-            f4 *L = &lds[b][0][0];
-#pragma unroll
-            for (int r = 0; r < RY; ++r)
-                L[(4 + ly * RY + r) * LW + lx + 1] = q[(s + 4) % QS][r];
-#pragma unroll
-            for (int h = 0; h < HPT; ++h)
-                if (h_lds[h] >= 0)
-                    L[h_lds[h]] = hv[cur_set][h];
-            __syncthreads();
-
-            // y taps: LDS rows ly*RY - 4 .. ly*RY + RY + 3 of this column,
-            // own rows straight from the queue
-            f4 ycol[RY + 8];
-#pragma unroll
-            for (int j = 0; j < RY + 8; ++j) {
-                if (j >= 4 && j < 4 + RY)
-                    ycol[j] = q[(s + 4) % QS][j - 4];
-                else
-                    ycol[j] = L[(ly * RY + j) * LW + lx + 1];
-            }
-
-            const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.out, pbytes, z);
-#pragma unroll
-            for (int r = 0; r < RY; ++r) {
-                const f4 xl = L[(4 + ly * RY + r) * LW + lx];
-                const f4 xr = L[(4 + ly * RY + r) * LW + lx + 2];
-                const f4 ctr = q[(s + 4) % QS][r];
-                float xs[12];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    xs[e] = xl.v[e];
-                    xs[4 + e] = ctr.v[e];
-                    xs[8 + e] = xr.v[e];
-                }
-                f4 out;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    float lap;
-                    if constexpr (SCALED) {
-                        lap = c.ctr * ctr.v[e];
-#pragma unroll
-                        for (int m = 1; m <= 4; ++m) {
-                            lap = fmaf(c.cx[m - 1], xs[4 + e + m] + xs[4 + e - m], lap);
-                            lap = fmaf(c.cy[m - 1], ycol[4 + r + m].v[e] + ycol[4 + r - m].v[e], lap);
-                            lap = fmaf(c.cz[m - 1],
-                                       q[(s + 4 + m) % QS][r].v[e] + q[(s + 4 - m + QS) % QS][r].v[e],
-                                       lap);
-                        }
-                    } else {
-                        const float u2 = 2.f * ctr.v[e];
-                        lap = 0.f;
-#pragma unroll
-                        for (int m = 1; m <= 4; ++m) {
-                            lap = fmaf(c.cx[m - 1], (xs[4 + e + m] + xs[4 + e - m]) - u2, lap);
-                            lap = fmaf(c.cy[m - 1], (ycol[4 + r + m].v[e] + ycol[4 + r - m].v[e]) - u2,
-                                       lap);
-                            lap = fmaf(c.cz[m - 1],
-                                       (q[(s + 4 + m) % QS][r].v[e] + q[(s + 4 - m + QS) % QS][r].v[e]) -
-                                           u2,
-                                       lap);
-                        }
-                    }
-                    const float g = gxv.v[e] * gyv[r] * gzv[cur_set];
-                    if constexpr (IMG) {
-                        // imaging term: (phi / k) G lap a
-                        out.v[e] = pv[cur_set][r].v[e] / kv[cur_set][r].v[e] * g * lap;
-                    } else if constexpr (ADJ) {
-                        const float t = fmaf(kv[cur_set][r].v[e], lap, 2.f * ctr.v[e]);
-                        out.v[e] = fmaf(-g * g, pv[cur_set][r].v[e], t);
-                    } else {
-                        float t, pe;
-                        if constexpr (SCALED) {
-                            t = fmaf(kv[cur_set][r].v[e], lap, fd.two_a * ctr.v[e]);
-                            pe = fd.b * pv[cur_set][r].v[e];
-                        } else {
-                            t = fmaf(kv[cur_set][r].v[e], lap, 2.f * ctr.v[e]);
-                            pe = pv[cur_set][r].v[e];
-                        }
-                        t = fmaf(-g, pe, t);
-                        out.v[e] = g * t;
-                    }
-                }
-                if constexpr (IMG) {
-                    // the accumulator has the field layout with 8-byte cells,
-                    // so a full 4-cell group is two aligned 16-byte pairs
-                    if (col_full) {
-                        double2 *gp = reinterpret_cast<double2 *>(
-                            a.grad + (long long)(z + kGhost) * a.plane + own_in[r] / EB);
-                        if (row_int[r]) {
-                            double2 g0 = gp[0], g1 = gp[1];
-                            g0.x += (double)out.v[0];
-                            g0.y += (double)out.v[1];
-                            g1.x += (double)out.v[2];
-                            g1.y += (double)out.v[3];
-                            gp[0] = g0;
-                            gp[1] = g1;
-                        }
-                    } else if (row_int[r]) {
-                        double *gp = a.grad + (long long)(z + kGhost) * a.plane + own_in[r] / EB;
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (x + e < a.nx)
-                                gp[e] += (double)out.v[e];
-                    }
-                    continue;
-                }
-                if (src_r == r && z == a.src_z) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (e == src_e)
-                            out.v[e] += sval;
-                }
-                if (col_full) {
-                    store4<KIND>(ro, own_in[r], out, 1.f);
-                    if constexpr (SCALED) {
-                        if (row_int[r]) {
-#pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                tmax = fmaxf(tmax, fabsf(out.v[e]));
-                        }
-                    }
-                } else if (row_int[r]) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const bool in = x + e < a.nx;
-                        store1<KIND>(ro, in ? own_in[r] + EB * e : kOff, out.v[e], 1.f);
-                        if constexpr (SCALED)
-                            tmax = in ? fmaxf(tmax, fabsf(out.v[e])) : tmax;
-                    }
-                }
-            }
-            return true;
-        });
-    }
-
-    if constexpr (SCALED)
-        fold_max(a, tmax * sc.out);
-    sample_receivers<KIND>(a, lid, tid, NT, sc.out);
-}
-
-template <int KIND, int TXV, int TY, int RY>
-__global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
-{
-    const int lid = logical_wg();
-    if (lid >= a.nwg)
-        return;
-    tile_step<KIND, TXV, TY, RY>(a, lid);
-}
-
-template <int MODE, int TXV, int TY, int RY>
-__global__ __launch_bounds__(TXV *TY) void adjoint_tiled(StepArgs a)
-{
-    const int lid = logical_wg();
-    if (lid >= a.nwg)
-        return;
-    tile_step<WAVE_F32, TXV, TY, RY, MODE>(a, lid);
-}
-
-// Adds k * trace_grad[row][r] at the receiver cells: one thread per distinct
-// cell, summing its receivers in a fixed order (deterministic, no atomics).
-__global__ void inject_receivers(float *phi, const float *__restrict__ k, const long long *__restrict__ cell_off,
-                                 const int *__restrict__ cell_start, const int *__restrict__ cell_rec,
-                                 int ncells, const float *__restrict__ tg_row)
-{
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < ncells) {
-        float s = 0.f;
-        for (int i = cell_start[c]; i < cell_start[c + 1]; ++i)
-            s += tg_row[cell_rec[i]];
-        const long long o = cell_off[c];
-        phi[o] = fmaf(k[o], s, phi[o]);
-    }
-}
-
-// misfit = 0.5 sum (traces - d_obs)^2 in FP64 (one work-group, fixed
-// summation order, differences taken exactly); residual = traces - d_obs
-// rounded to FP32 when requested.
-__global__ __launch_bounds__(1024) void misfit_kernel(const float *__restrict__ tr,
-                                                      const float *__restrict__ obs, long long n,
-                                                      float *residual, double *out)
-{
-    __shared__ double part[1024];
-    double acc = 0.0;
-    for (long long i = threadIdx.x; i < n; i += blockDim.x) {
-        const double r = (double)tr[i] - (double)obs[i];  // exact
-        if (residual)
-            residual[i] = (float)r;  // == the FP32 difference
-        acc += r * r;
-    }
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = 512; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            part[threadIdx.x] += part[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        *out = 0.5 * part[0];
-}
-
-// dense[z][y][x] (+)= acc at the interior cells of the field layout.
-__global__ __launch_bounds__(256) void grad_to_dense(const double *__restrict__ acc, double *dense, int nx,
-                                                    int ny, int nz, int px, int x0, long long plane,
-                                                    int accumulate)
-{
-    const long long n = (long long)nx * ny * nz;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int x = (int)(i % nx);
-        const int y = (int)((i / nx) % ny);
-        const int z = (int)(i / ((long long)nx * ny));
-        const double v = acc[(long long)(z + kGhost) * plane + (long long)(y + kGhost) * px + x0 + x];
-        dense[i] = accumulate ? dense[i] + v : v;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// many shots per launch
-
-// A shot of a batched run.  `a` holds the shot's arguments with the buffer
-// roles of the run's first step (cur = u^{n0}, nxt = u^{n0-1}); step j of
-// the run swaps them when j is odd and offsets the trace row and source.
-struct ShotDesc {
-    StepArgs a;
-    float *traces;     // trace buffer base (row n at traces + n * nrec), or NULL
-    int nrec;
-    int n0;            // step counter at the start of the run
-    const float *src;  // source values of the run's steps, or NULL (then no source)
-};
-
-// Work items of a batched step: (shot, tile and z-chunk of that shot),
-// split into 8 contiguous ranges of about equal work, one per XCD.
-struct BatchItems {
-    const int *shot;       // [items] shot (index into the group's descriptors)
-    const int *lid;        // [items] tile/chunk number within the shot
-    const int *xcd_start;  // [9] item range of each XCD
-    int *counters;         // [2][8] tickets of the current and the next step
-};
-
-// One time step of every shot in a group, as a persistent launch: the grid
-// holds as many work-groups as fit on the GPU at once; work-group b runs on
-// XCD b % 8 (blocks are dealt to the XCDs round-robin) and takes items of
-// that XCD's range by atomic ticket until the range is exhausted, so long
-// and short items balance dynamically while neighbouring tiles still share
-// an XCD's L2.  Step j draws from counter set j & 1 and clears set
-// (j + 1) & 1 for the next step (which starts only after this one ends).
-template <int KIND, int TXV, int TY, int RY>
-__global__ __launch_bounds__(TXV *TY) void step_batch(const ShotDesc *__restrict__ shots,
-                                                       BatchItems it, int j)
-{
-    __shared__ int ticket;
-    const int xcd = blockIdx.x & 7;
-    int *cnt = it.counters + 8 * (j & 1);
-    if (blockIdx.x == 0 && threadIdx.x < 8)
-        it.counters[8 * ((j + 1) & 1) + threadIdx.x] = 0;
-    const int first = it.xcd_start[xcd], last = it.xcd_start[xcd + 1];
-    for (;;) {
-        if (threadIdx.x == 0)
-            ticket = atomicAdd(&cnt[xcd], 1);
-        __syncthreads();
-        const int item = first + ticket;
-        __syncthreads();  // all threads have read the ticket (and left the LDS of the last item)
-        if (item >= last)
-            break;
-        const ShotDesc &d = shots[it.shot[item]];
-        StepArgs a = d.a;
-        if (j & 1) {
-            const void *t = a.cur;
-            a.cur = a.nxt;
-            a.nxt = const_cast<void *>(t);
-        }
-        a.out = a.nxt;  // in place
-        const int n = d.n0 + j;
-        a.step = n & 0x3fffffff;
-        a.trace_row = d.traces ? d.traces + (size_t)n * d.nrec : nullptr;
-        a.src_ptr = d.src ? d.src + j : nullptr;
-        a.src_val = 0.f;
-        if (!d.src)
-            a.src_z = -1;  // no source values given: no injection
-        tile_step<KIND, TXV, TY, RY>(a, it.lid[item]);
-    }
-}
-
-// Clears both ticket sets at the start of a batched run (a kernel rather
-// than a memset, so that it can sit in a captured graph).
-__global__ void clear_counters(int *c)
-{
-    if (threadIdx.x < 16)
-        c[threadIdx.x] = 0;
-}
-
-// One thread per interior cell, every tap read from global memory: a
-// deliberately plain kernel used to cross-check the tiled one.  Same FP32
-// operations in the same order, so the two agree bit for bit.
-template <int KIND>
-__global__ __launch_bounds__(256) void step_naive(StepArgs a)
-{
-    constexpr bool SCALED = Store<KIND>::scaled;
-    Scales sc{1.f, 1.f, 1.f, 1.f, 0};
-    Folded fd{a.c, 2.f, 1.f};
-    if constexpr (SCALED) {
-        sc = step_scales(a);
-        publish_scale(a, sc, blockIdx.x, threadIdx.x);
-        fd = fold_scales(a.c, sc, a.k_scale);
-    }
-    const Coefs &c = fd.c;
-    const long long n = (long long)a.nx * a.ny * a.nz;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    float amax = 0.f;
-    if (i < n) {
-        const int x = (int)(i % a.nx);
-        const int y = (int)((i / a.nx) % a.ny);
-        const int z = (int)(i / ((long long)a.nx * a.ny));
-        const long long p =
-            (long long)(z + kGhost) * a.plane + (long long)(y + kGhost) * a.px + a.x0 + x;
-        auto U = [&](long long q) { return read_elem<KIND>(a.cur, q, 1.f); };
-        const float u = U(p);
-        // same form and order as the tiled kernel (difference form for FP32)
-        const float u2 = SCALED ? 0.f : 2.f * u;
-        float lap = SCALED ? c.ctr * u : 0.f;
-        for (int m = 1; m <= 4; ++m) {
-            lap = fmaf(c.cx[m - 1], (U(p + m) + U(p - m)) - u2, lap);
-            lap = fmaf(c.cy[m - 1], (U(p + (long long)m * a.px) + U(p - (long long)m * a.px)) - u2, lap);
-            lap = fmaf(c.cz[m - 1], (U(p + m * a.plane) + U(p - m * a.plane)) - u2, lap);
-        }
-        const float g = a.gx[x] * a.gy[y] * a.gz[z];
-        const float kk = read_elem<KIND>(a.k, p, 1.f);
-        const float pp = read_elem<KIND>(a.nxt, p, 1.f);
-        float t, pe;
-        if constexpr (SCALED) {
-            t = fmaf(kk, lap, fd.two_a * u);
-            pe = fd.b * pp;
-        } else {
-            t = fmaf(kk, lap, 2.f * u);
-            pe = pp;
-        }
-        t = fmaf(-g, pe, t);
-        float v = g * t;
-        if (z == a.src_z && y == a.src_y && x == a.src_x)
-            v += src_value(a) * sc.out_inv;
-        if constexpr (KIND == WAVE_F32) {
-            static_cast<float *>(a.out)[p] = v;
-        } else {
-            static_cast<unsigned short *>(a.out)[p] = (unsigned short)Store<KIND>::enc(v);
-            amax = fabsf(v);
-        }
-    }
-    if constexpr (SCALED)
-        fold_max(a, amax * sc.out);
-}
-
-// Receivers for the naive kernel (separate launch: it has no tile
-// epilogue).  With 16-bit storage the scale of u^{n+1} is the one the step
-// just published.
-template <int KIND>
-__global__ void sample_naive(const void *__restrict__ f, const long long *__restrict__ off, int nrec,
-                             float *row, const int *exps, int slot)
-{
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < nrec) {
-        const float scale = Store<KIND>::scaled ? ldexpf(1.f, exps[slot]) : 1.f;
-        row[r] = read_elem<KIND>(f, off[r], scale);
-    }
-}
-
-// Max, min and a non-finite flag of an FP32 k over the interior, as float
-// bit patterns (valid for non-negative values; negatives raise the flag).
-__global__ __launch_bounds__(256) void k_range(const float *__restrict__ k, int nx, int ny, int nz,
-                                               int px, int x0, long long plane, unsigned *out)
-{
-    __shared__ unsigned smax[256], smin[256], sbad[256];
-    unsigned mx = 0u, mn = 0x7f800000u, bad = 0u;
-    const long long n = (long long)nx * ny * nz;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int x = (int)(i % nx);
-        const int y = (int)((i / nx) % ny);
-        const int z = (int)(i / ((long long)nx * ny));
-        const float v = k[(long long)(z + kGhost) * plane + (long long)(y + kGhost) * px + x0 + x];
-        if (!(v >= 0.f) || !(v < INFINITY)) {
-            bad = 1u;
-        } else {
-            const unsigned b = __float_as_uint(v);
-            mx = max(mx, b);
-            mn = min(mn, b);
-        }
-    }
-    const int t = threadIdx.x;
-    smax[t] = mx;
-    smin[t] = mn;
-    sbad[t] = bad;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) {
-            smax[t] = max(smax[t], smax[t + s]);
-            smin[t] = min(smin[t], smin[t + s]);
-            sbad[t] |= sbad[t + s];
-        }
-        __syncthreads();
-    }
-    if (t == 0) {
-        atomicMax(&out[0], smax[0]);
-        atomicMin(&out[1], smin[0]);
-        atomicOr(&out[2], sbad[0]);
-    }
-}
-
-// Interior copy between two layouts with an exact power-of-two rescale:
-// FP32 k into 16-bit storage (init), or a field of any storage into FP32
-// (export).  `exps`/`slot` select a device exponent for the source scale.
-template <int SRC, int DST>
-__global__ __launch_bounds__(256) void convert_interior(const void *__restrict__ src, void *dst, int nx,
-                                                        int ny, int nz, int spx, int sx0,
-                                                        long long splane, int dpx, int dx0,
-                                                        long long dplane, float scale,
-                                                        const int *exps, int slot)
-{
-    const long long n = (long long)nx * ny * nz;
-    const float sc = exps ? ldexpf(1.f, exps[slot]) : scale;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int x = (int)(i % nx);
-        const int y = (int)((i / nx) % ny);
-        const int z = (int)(i / ((long long)nx * ny));
-        const long long si = (long long)(z + kGhost) * splane + (long long)(y + kGhost) * spx + sx0 + x;
-        const long long di = (long long)(z + kGhost) * dplane + (long long)(y + kGhost) * dpx + dx0 + x;
-        const float v = read_elem<SRC>(src, si, 1.f);
-        if constexpr (DST == WAVE_F32)
-            static_cast<float *>(dst)[di] = v * sc;
-        else
-            static_cast<unsigned short *>(dst)[di] = (unsigned short)Store<DST>::enc(v * sc);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // host side
 

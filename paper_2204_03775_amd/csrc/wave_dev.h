@@ -1,0 +1,139 @@
+// Types, constants and kernel declarations shared by the host code of
+// libwave.so (wave.hip) and its kernel translation units (k_*.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "wave.h"
+
+namespace wavek {
+
+
+constexpr int kGhost = 4;
+constexpr int kRowAlignBytes = 128;  // interior rows start on this boundary
+
+// 8th-order central second-derivative weights (four points each way).
+constexpr double kC0 = -205.0 / 72.0;
+constexpr double kCm[4] = {8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+// max over wavenumbers of |c0 + 2 sum c_m cos(m kh)|, reached at kh = pi;
+// it also equals |c0| + 2 sum |c_m|, which bounds |lap u| by this times
+// max|u| sum 1/h^2.
+constexpr double kSymbolMax = 2048.0 / 315.0;
+
+// largest scaled magnitude a 16-bit field is written with (2^14)
+constexpr int kScaledTopExp = 14;
+
+constexpr int elem_bytes(int dtype) { return dtype == WAVE_F32 ? 4 : 2; }
+
+struct alignas(16) f4 {
+    float v[4];
+};
+
+struct Coefs {
+    float ctr;    // c0 * (1/dx^2 + 1/dy^2 + 1/dz^2): the centre counted once
+    float cx[4];  // c_m / dx^2
+    float cy[4];
+    float cz[4];
+};
+
+struct StepArgs {
+    const void *k;
+    const void *cur;
+    void *nxt;  // u^{n-1} (adjoint: phi^{m+2}; imaging: phi^m)
+    const float *__restrict__ gx;
+    const float *__restrict__ gy;
+    const float *__restrict__ gz;
+    Coefs c;
+    int nx, ny, nz;
+    int px;             // row pitch in elements
+    int x0;             // element offset of interior x = 0 in a row
+    long long plane;    // elements per plane
+    int nxq;            // ceil(nx / 4): 4-cell columns holding interior cells
+    int ntx, nty, nchunks, zc, nwg;
+    int src_z, src_y, src_x;  // src_z < 0: no source
+    const float *src_ptr;     // device value of this step, or NULL
+    float src_val;            // used when src_ptr is NULL
+    const int *rec_start;     // [nwg + 1] receiver ranges per work-group
+    const long long *rec_off; // element offset of each receiver
+    const int *rec_idx;       // receiver number
+    float *trace_row;         // row of this step, or NULL
+    // 16-bit storage only
+    int step;                 // n: this launch writes u^{n+1}
+    float k_scale;            // k = stored k * k_scale
+    int *exps;                // [4] exponent of u^m in slot m & 3
+    unsigned *maxes;          // [4] max |u^m| (float bits) in slot m & 3
+    // output field: == nxt for the in-place step (each cell is read, then
+    // written, by the same thread), a separate level otherwise
+    void *out;
+    // imaging only: FP64 accumulator in the field layout (8-byte cells)
+    double *grad;
+};
+
+// What a tiled launch computes (FP32 storage only for the last two):
+//   kFwd  u^{n+1} = G (2 u^n - G u^{n-1} + k lap u^n) (+ source, receivers);
+//   kAdj  the adjoint step phi^m = 2 psi + k lap psi - G^2 phi^{m+2} with
+//         psi = G phi^{m+1} (G applied to every loaded value);
+//   kImg  grad += (phi / k) G lap a: the imaging term of one adjoint step.
+constexpr int kFwd = 0;
+constexpr int kAdj = 1;
+constexpr int kImg = 2;
+
+// A shot of a batched run.  `a` holds the shot's arguments with the buffer
+// roles of the run's first step (cur = u^{n0}, nxt = u^{n0-1}); step j of
+// the run swaps them when j is odd and offsets the trace row and source.
+struct ShotDesc {
+    StepArgs a;
+    float *traces;     // trace buffer base (row n at traces + n * nrec), or NULL
+    int nrec;
+    int n0;            // step counter at the start of the run
+    const float *src;  // source values of the run's steps, or NULL (then no source)
+};
+
+// Work items of a batched step: (shot, tile and z-chunk of that shot),
+// split into 8 contiguous ranges of about equal work, one per XCD.
+struct BatchItems {
+    const int *shot;       // [items] shot (index into the group's descriptors)
+    const int *lid;        // [items] tile/chunk number within the shot
+    const int *xcd_start;  // [9] item range of each XCD
+    int *counters;         // [2][8] tickets of the current and the next step
+};
+
+// Tile shapes (float4 columns x thread rows x rows per thread) of the tiled
+// kernels, in the order of the variant table.
+#define WAVE_TILE_SHAPES(X)                                                                       \
+    X(16, 16, 1) X(32, 8, 1) X(32, 8, 2) X(16, 16, 2) X(32, 16, 1) X(64, 4, 2) X(16, 8, 2)       \
+    X(32, 8, 4) X(64, 8, 1) X(16, 32, 1) X(32, 16, 2) X(64, 8, 2)
+
+// kernels (defined in the k_*.hip translation units)
+template <int KIND, int TXV, int TY, int RY>
+__global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a);
+template <int MODE, int TXV, int TY, int RY>
+__global__ __launch_bounds__(TXV *TY) void adjoint_tiled(StepArgs a);
+template <int KIND, int TXV, int TY, int RY>
+__global__ __launch_bounds__(TXV *TY) void step_batch(const ShotDesc *__restrict__ shots, BatchItems it,
+                                                       int j);
+template <int KIND>
+__global__ __launch_bounds__(256) void step_naive(StepArgs a);
+template <int KIND>
+__global__ void sample_naive(const void *__restrict__ f, const long long *__restrict__ off, int nrec,
+                             float *row, const int *exps, int slot);
+template <int SRC, int DST>
+__global__ __launch_bounds__(256) void convert_interior(const void *__restrict__ src, void *dst, int nx,
+                                                        int ny, int nz, int spx, int sx0, long long sp,
+                                                        int dpx, int dx0, long long dp, float scale,
+                                                        const int *exps, int slot);
+__global__ void clear_counters(int *c);
+__global__ __launch_bounds__(256) void k_range(const float *__restrict__ k, int nx, int ny, int nz,
+                                               int px, int x0, long long plane, unsigned *out);
+__global__ void inject_receivers(float *phi, const float *__restrict__ k,
+                                 const long long *__restrict__ cell_off,
+                                 const int *__restrict__ cell_start, const int *__restrict__ cell_rec,
+                                 int ncells, const float *__restrict__ tg_row);
+__global__ __launch_bounds__(1024) void misfit_kernel(const float *__restrict__ tr,
+                                                      const float *__restrict__ obs, long long n,
+                                                      float *residual, double *out);
+__global__ __launch_bounds__(256) void grad_to_dense(const double *__restrict__ acc, double *dense, int nx,
+                                                    int ny, int nz, int px, int x0, long long plane,
+                                                    int accumulate);
+
+}  // namespace wavek

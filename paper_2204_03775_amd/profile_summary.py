@@ -4,6 +4,10 @@
       kernel-trace statistics (<prefix>_kernel_stats.csv): the kernels by
       total time, with calls and average duration;
 
+  python -m paper_2204_03775_amd.profile_summary kernels --fetch F --write W \\
+      --fetch-probe PF --write-probe PW --title T --commands CMDS --out FILE.md
+      the same scaling for every library kernel, per kernel and grid size;
+
   python -m paper_2204_03775_amd.profile_summary traffic \\
       --fetch-step F --write-step W --fetch-probe PF --write-probe PW \\
       --kernel NAME --zchunk ZC --points N --commands CMDS --out-json J --out-md M
@@ -12,8 +16,9 @@
       counter onto the known traffic of the copy probe (8 bytes per element:
       one read, one write).
 
-The traffic record carries the SHA-256 of the kernel source it was taken
-on; bench.py reports it only while the source is unchanged.
+The traffic record carries the SHA-256 of the step kernel's sources
+(wave_dev.h, wave_step.h, k_fwd_f32.hip) it was taken on; bench.py
+reports it only while they are unchanged.
 """
 from __future__ import annotations
 
@@ -25,7 +30,16 @@ import json
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(_HERE, "csrc", "wave.hip")
+KERNEL_SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("wave_dev.h", "wave_step.h", "k_fwd_f32.hip")]
+
+
+def source_digest() -> str:
+    """SHA-256 over the FP32 step kernel's sources (same as bench.py's)."""
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def _short(name: str, n: int = 90) -> str:
@@ -79,7 +93,7 @@ def traffic(a):
     algo_read, algo_write = 12 * a.points, 4 * a.points
     rec = {
         "kernel": a.kernel, "zchunk": a.zchunk,
-        "source_sha256": hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest(),
+        "source_sha256": source_digest(),
         "dispatches": len(fs[ks]),
         "fetch_kib_per_dispatch": round(avg(fs[ks]), 1),
         "write_kib_per_dispatch": round(avg(ws[pick(ws, "step_tiled")]), 1),
@@ -109,6 +123,37 @@ def traffic(a):
     print("\n".join(lines))
 
 
+def kernels(a):
+    """Scaled read / write bytes per dispatch of every library kernel, per
+    launch size (kernels of one name and grid size are averaged together)."""
+    def per(path, ctr):
+        d = collections.defaultdict(list)
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == ctr:
+                    d[(r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+        return d
+    fs, ws = per(a.fetch, "FETCH_SIZE"), per(a.write, "WRITE_SIZE")
+    fp, wp = per(a.fetch_probe, "FETCH_SIZE"), per(a.write_probe, "WRITE_SIZE")
+    avg = lambda v: sum(v) / len(v)
+    copy_kib = a.probe_elements * 4 / 1024.0
+    f_scale = copy_kib / avg(next(v for k, v in fp.items() if "copy_k" in k[0]))
+    w_scale = copy_kib / avg(next(v for k, v in wp.items() if "copy_k" in k[0]))
+    lines = [f"# {a.title}", "",
+             f"FETCH_SIZE x {f_scale:.4f} and WRITE_SIZE x {w_scale:.4f} (copy probe, "
+             f"{a.probe_elements} floats).  Rows group dispatches by kernel and grid size.", "",
+             "| kernel | grid (work-items) | dispatches | read MB / dispatch | written MB / dispatch |",
+             "|---|---:|---:|---:|---:|"]
+    rows = sorted(((k, v) for k, v in fs.items() if a.match in k[0]), key=lambda kv: -avg(kv[1]) * len(kv[1]))
+    for (name, grid), v in rows:
+        w = ws.get((name, grid), [0.0])
+        lines.append(f"| `{_short(name, 70)}` | {grid} | {len(v)} | {avg(v) * f_scale * 1024 / 1e6:.2f} | "
+                     f"{avg(w) * w_scale * 1024 / 1e6:.2f} |")
+    lines += ["", "Commands:", ""] + [f"    {c}" for c in a.commands]
+    open(a.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -123,9 +168,17 @@ def main():
     t.add_argument("--points", type=int, required=True)
     t.add_argument("--probe-elements", type=int, required=True)
     t.add_argument("--commands", nargs="+", required=True)
+    k = sub.add_parser("kernels")
+    for name in ("fetch", "write", "fetch-probe", "write-probe", "out", "title"):
+        k.add_argument("--" + name, required=True)
+    k.add_argument("--match", default="wavek::")
+    k.add_argument("--probe-elements", type=int, required=True)
+    k.add_argument("--commands", nargs="+", required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
         stats(a.prefix, a.command, a.out)
+    elif a.cmd == "kernels":
+        kernels(a)
     else:
         traffic(a)
 
