@@ -201,6 +201,12 @@ int wave_forward_checkpointed(wave_ctx *ctx, int32_t nt, const float *src_dev, i
  * traces and step counter are left as the forward run left them. */
 int wave_adjoint(wave_ctx *ctx, const float *trace_grad_dev, double *grad_dev, int32_t accumulate);
 
+/* The adjoint run normally makes phi^{m-1} and adds the imaging term of
+ * phi^m in one pass over the grid (36 instead of 44 bytes per cell and
+ * step); on = 0 selects two separate passes.  Both give the same result
+ * bit for bit; the switch exists for that cross-check. */
+int wave_set_adjoint_fusion(wave_ctx *ctx, int32_t on);
+
 /* Steps, segment length, segments and bytes of checkpoint/level storage of
  * the last checkpointed forward run (nt = 0 when there is none). */
 int wave_grad_info(const wave_ctx *ctx, int32_t *nt, int32_t *every, int32_t *segments, int64_t *bytes);

@@ -30,7 +30,7 @@ struct Variant {
     const char *name;
     StepKernel fn[3];  // by storage type; all NULL for "auto" and "naive"
     BatchKernel batch[3];
-    StepKernel adj[2];  // adjoint step, imaging step (FP32)
+    StepKernel adj[3];  // adjoint step, imaging step, fused adjoint + imaging (FP32)
     int txv, ty, ry;
 };
 
@@ -39,11 +39,11 @@ struct Variant {
      step_tiled<WAVE_BF16, TXV, TY, RY>},                                                         \
     {step_batch<WAVE_F32, TXV, TY, RY>, step_batch<WAVE_F16, TXV, TY, RY>,                        \
      step_batch<WAVE_BF16, TXV, TY, RY>},                                                         \
-    {adjoint_tiled<kAdj, TXV, TY, RY>, adjoint_tiled<kImg, TXV, TY, RY>}
+    {adjoint_tiled<kAdj, TXV, TY, RY>, adjoint_tiled<kImg, TXV, TY, RY>, adjoint_tiled<kFus, TXV, TY, RY>}
 
 const Variant kVariants[] = {
-    {"auto", {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr}, 0, 0, 0},
-    {"naive", {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr}, 0, 0, 0},
+    {"auto", {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, 0, 0, 0},
+    {"naive", {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, 0, 0, 0},
     {"t64x16_r1", TILED(16, 16, 1), 16, 16, 1},
     {"t128x8_r1", TILED(32, 8, 1), 32, 8, 1},
     {"t128x16_r2", TILED(32, 8, 2), 32, 8, 2},
@@ -123,6 +123,7 @@ struct wave_ctx {
     int v_used = 0, zc_used = 0;
     int ntx = 0, nty = 0, nchunks = 0, nwg = 0, grid = 0;
     wave_grad_state g;
+    bool fuse_adjoint = true;  // adjoint step and imaging term in one pass
     std::string err;
 };
 
@@ -307,6 +308,7 @@ StepArgs make_args(const wave_ctx *c)
     a.maxes = reinterpret_cast<unsigned *>(c->ring + 4);
     a.out = c->prev;
     a.grad = nullptr;
+    a.aux = nullptr;
     return a;
 }
 
@@ -451,21 +453,29 @@ Geo ctx_geo(const wave_ctx *c)
     return g;
 }
 
-// The adjoint and imaging steps use the context's tiling (the automatic one
-// when the context runs the naive kernel).
+// The adjoint and imaging steps use the context's tiling when one was
+// configured, else their own automatic choice: the fused pass holds two
+// stencil fields, and at 256 x 8 tiles it needs more than the 256 registers
+// two waves per SIMD allow (it spills), while 128 x 16 tiles fit (241).
+constexpr int kAdjointAutoVariant = 6;  // t128x16_r1 for grids of >= 2^22 cells
+
 Geo adjoint_geo(const wave_ctx *c)
 {
-    return c->v_used == kNaive ? plan_geo(c->p.nx, c->p.ny, c->p.nz, 0, 0) : ctx_geo(c);
+    if (c->variant != 0 && c->v_used != kNaive)
+        return ctx_geo(c);
+    const long long pts = (long long)c->p.nx * c->p.ny * c->p.nz;
+    return plan_geo(c->p.nx, c->p.ny, c->p.nz, pts >= (1ll << 22) ? kAdjointAutoVariant : kSmallVariant, 0);
 }
 
 int enqueue_adjoint(wave_ctx *c, const Geo &geo, int mode, const void *cur, void *nxt, void *out,
-                    double *acc)
+                    double *acc, const void *aux = nullptr)
 {
     StepArgs a = make_args(c);
     a.cur = cur;
     a.nxt = nxt;
     a.out = out;
     a.grad = acc;
+    a.aux = aux;
     a.ntx = geo.ntx;
     a.nty = geo.nty;
     a.nchunks = geo.nchunks;
@@ -1036,32 +1046,69 @@ int wave_adjoint(wave_ctx *ctx, const float *trace_grad_dev, double *grad_dev, i
     HIP_TRY(ctx, hipMemsetAsync(g.acc, 0, ab, ctx->stream));
 
     const Geo geo = adjoint_geo(ctx);
-    void *A = g.phi[0], *B = g.phi[1];  // phi^{m+1}, phi^{m+2}
-    for (int m = g.nt; m >= 1; --m) {
-        // phi^m = 2 G phi^{m+1} + K L G phi^{m+1} - G^2 phi^{m+2}, over phi^{m+2}
-        rc = enqueue_adjoint(ctx, geo, kAdj, A, B, B, nullptr);
-        if (rc != WAVE_OK)
-            return rc;
-        std::swap(A, B);
-        // + K R^T (dJ/d traces row m-1)
+    // + K R^T (dJ/d traces, row m-1) into phi^m
+    auto inject = [&](void *phi, int m) -> int {
         if (g.ncells > 0) {
             hipLaunchKernelGGL(inject_receivers, dim3((g.ncells + 255) / 256), dim3(256), 0, ctx->stream,
-                               static_cast<float *>(A), static_cast<const float *>(ctx->k), g.cell_off,
+                               static_cast<float *>(phi), static_cast<const float *>(ctx->k), g.cell_off,
                                g.cell_start, g.cell_rec, g.ncells,
                                trace_grad_dev + (size_t)(m - 1) * ctx->nrec);
             HIP_TRY(ctx, hipGetLastError());
         }
-        // grad += (phi^m / k) G L a^{m-1}
-        const int seg = (m - 1) / g.every;
+        return WAVE_OK;
+    };
+    // the level a^l, recomputing its segment from the checkpoint if needed
+    auto level = [&](int64_t l, const void **out) -> int {
+        const int seg = int(l / g.every);
         if (g.held != seg) {
             const int64_t c0 = (int64_t)seg * g.every;
-            rc = forward_segment(ctx, seg, int(std::min<int64_t>(g.every, g.nt - c0)) - 1, false);
-            if (rc != WAVE_OK)
-                return rc;
+            const int r = forward_segment(ctx, seg, int(std::min<int64_t>(g.every, g.nt - c0)) - 1, false);
+            if (r != WAVE_OK)
+                return r;
         }
-        rc = enqueue_adjoint(ctx, geo, kImg, level_ptr(ctx, seg, m - 1), A, nullptr, g.acc);
+        *out = level_ptr(ctx, seg, l);
+        return WAVE_OK;
+    };
+    const void *lev = nullptr;
+    void *A = g.phi[0], *B = g.phi[1];  // phi^{m+1}, phi^{m+2}
+    if (ctx->fuse_adjoint) {
+        // phi^nt, then for m = nt .. 2 one pass makes phi^{m-1} and adds the
+        // imaging term of phi^m; the term of phi^1 closes the sum
+        rc = enqueue_adjoint(ctx, geo, kAdj, A, B, B, nullptr);
+        if (rc == WAVE_OK)
+            rc = inject(B, g.nt);
         if (rc != WAVE_OK)
             return rc;
+        std::swap(A, B);  // A = phi^m, B = phi^{m+1}
+        for (int m = g.nt; m >= 2; --m) {
+            if ((rc = level(m - 1, &lev)) != WAVE_OK)
+                return rc;
+            rc = enqueue_adjoint(ctx, geo, kFus, A, B, B, g.acc, lev);
+            if (rc == WAVE_OK)
+                rc = inject(B, m - 1);
+            if (rc != WAVE_OK)
+                return rc;
+            std::swap(A, B);
+        }
+        if ((rc = level(0, &lev)) != WAVE_OK)
+            return rc;
+        if ((rc = enqueue_adjoint(ctx, geo, kImg, lev, A, nullptr, g.acc)) != WAVE_OK)
+            return rc;
+    } else {
+        for (int m = g.nt; m >= 1; --m) {
+            // phi^m = 2 G phi^{m+1} + K L G phi^{m+1} - G^2 phi^{m+2}, over phi^{m+2}
+            rc = enqueue_adjoint(ctx, geo, kAdj, A, B, B, nullptr);
+            if (rc != WAVE_OK)
+                return rc;
+            std::swap(A, B);
+            if ((rc = inject(A, m)) != WAVE_OK)
+                return rc;
+            // grad += (G phi^m / k) L a^{m-1}
+            if ((rc = level(m - 1, &lev)) != WAVE_OK)
+                return rc;
+            if ((rc = enqueue_adjoint(ctx, geo, kImg, lev, A, nullptr, g.acc)) != WAVE_OK)
+                return rc;
+        }
     }
     const long long n = (long long)ctx->p.nx * ctx->p.ny * ctx->p.nz;
     hipLaunchKernelGGL(grad_to_dense, dim3((unsigned)std::min<long long>((n + 255) / 256, 8192)), dim3(256),
@@ -1069,6 +1116,14 @@ int wave_adjoint(wave_ctx *ctx, const float *trace_grad_dev, double *grad_dev, i
                        int(ctx->lay.pitch_x), int(ctx->lay.x_offset), (long long)ctx->lay.plane,
                        accumulate ? 1 : 0);
     HIP_TRY(ctx, hipGetLastError());
+    return WAVE_OK;
+}
+
+int wave_set_adjoint_fusion(wave_ctx *ctx, int32_t on)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    ctx->fuse_adjoint = on != 0;
     return WAVE_OK;
 }
 

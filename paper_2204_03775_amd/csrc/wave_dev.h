@@ -65,18 +65,23 @@ struct StepArgs {
     // output field: == nxt for the in-place step (each cell is read, then
     // written, by the same thread), a separate level otherwise
     void *out;
-    // imaging only: FP64 accumulator in the field layout (8-byte cells)
+    // imaging: FP64 accumulator in the field layout (8-byte cells)
     double *grad;
+    // fused adjoint step: the forward level whose Laplacian the imaging term needs
+    const void *aux;
 };
 
 // What a tiled launch computes (FP32 storage only for the last two):
 //   kFwd  u^{n+1} = G (2 u^n - G u^{n-1} + k lap u^n) (+ source, receivers);
 //   kAdj  the adjoint step phi^m = 2 psi + k lap psi - G^2 phi^{m+2} with
 //         psi = G phi^{m+1} (G applied to every loaded value);
-//   kImg  grad += (phi / k) G lap a: the imaging term of one adjoint step.
+//   kImg  grad += (G phi / k) lap a: the imaging term of one adjoint step;
+//   kFus  kAdj from phi^m, phi^{m+1} together with the kImg term of phi^m
+//         and a = aux (the same arithmetic, bit for bit, in one pass).
 constexpr int kFwd = 0;
 constexpr int kAdj = 1;
 constexpr int kImg = 2;
+constexpr int kFus = 3;
 
 // A shot of a batched run.  `a` holds the shot's arguments with the buffer
 // roles of the run's first step (cur = u^{n0}, nxt = u^{n0-1}); step j of

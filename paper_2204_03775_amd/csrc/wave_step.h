@@ -306,9 +306,13 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
     constexpr int QS = 10;                   // queue slots: 9 live planes + 1 being filled
     constexpr unsigned EB = Store<KIND>::bytes;
     constexpr bool SCALED = Store<KIND>::scaled;
-    constexpr bool ADJ = MODE == kAdj, IMG = MODE == kImg;
+    constexpr bool FUS = MODE == kFus;            // adjoint step + imaging term of the step after it
+    constexpr bool ADJ = MODE == kAdj || FUS;     // the stencil field is phi, scaled by G on load
+    constexpr bool IMG = MODE == kImg;
     static_assert(MODE == kFwd || KIND == WAVE_F32, "adjoint and imaging steps are FP32 only");
     __shared__ f4 lds[2][LH][LW];
+    // second stencil field (the forward level of the imaging term), fused mode only
+    __shared__ f4 lds2[FUS ? 2 : 1][FUS ? LH : 1][FUS ? LW : 1];
 
     const int tx = lid % a.ntx;
     const int rest = lid / a.ntx;
@@ -442,12 +446,19 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
         return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(gz_r, 4u * unsigned(z), 0, 0));
     };
     f4 q[QS][RY];
+    f4 q2[FUS ? QS : 1][RY];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const __amdgpu_buffer_rsrc_t rc = plane_rsrc(a.cur, pbytes, z0 - 4 + i);
 #pragma unroll
         for (int r = 0; r < RY; ++r)
             q[i][r] = load4<KIND, kKeep>(rc, own_ld[r], 1.f);
+        if constexpr (FUS) {
+            const __amdgpu_buffer_rsrc_t ra = plane_rsrc(a.aux, pbytes, z0 - 4 + i);
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+                q2[i][r] = load4<KIND, kKeep>(ra, own_ld[r], 1.f);
+        }
         if constexpr (ADJ) {
             const float gzi = gz_at(z0 - 4 + i);
 #pragma unroll
@@ -461,6 +472,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
     // values of the next plane, loaded one plane ahead into the set of the
     // other parity (no copies, so no wait before the next loads are issued)
     f4 pv[2][RY], kv[2][RY], hv[2][HPT];
+    f4 hv2[FUS ? 2 : 1][FUS ? HPT : 1];
     float gzv[2], gzq[2];  // g_z of the plane and (adjoint) of the queue plane z + 4
     auto prefetch = [&](int z, int slot, int set) {
         const __amdgpu_buffer_rsrc_t rq = plane_rsrc(a.cur, pbytes, z + 4);
@@ -476,6 +488,16 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
 #pragma unroll
         for (int h = 0; h < HPT; ++h)
             hv[set][h] = load4<KIND, kKeep>(rh, h_b[h], 1.f);
+        if constexpr (FUS) {
+            const __amdgpu_buffer_rsrc_t raq = plane_rsrc(a.aux, pbytes, z + 4);
+            const __amdgpu_buffer_rsrc_t rah = plane_rsrc(a.aux, pbytes, z);
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+                q2[slot][r] = load4<KIND, kKeep>(raq, own_ld[r], 1.f);
+#pragma unroll
+            for (int h = 0; h < HPT; ++h)
+                hv2[set][h] = load4<KIND, kKeep>(rah, h_b[h], 1.f);
+        }
         gzv[set] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(gz_r, 4u * z, 0, 0));
         if constexpr (ADJ)
             gzq[set] = gz_at(z + 4);
@@ -517,6 +539,16 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
             for (int h = 0; h < HPT; ++h)
                 if (h_lds[h] >= 0)
                     L[h_lds[h]] = hv[cur_set][h];
+            f4 *L2 = &lds2[FUS ? b : 0][0][0];
+            if constexpr (FUS) {
+#pragma unroll
+                for (int r = 0; r < RY; ++r)
+                    L2[(4 + ly * RY + r) * LW + lx + 1] = q2[(s + 4) % QS][r];
+#pragma unroll
+                for (int h = 0; h < HPT; ++h)
+                    if (h_lds[h] >= 0)
+                        L2[h_lds[h]] = hv2[cur_set][h];
+            }
             __syncthreads();
 
             // y taps: LDS rows ly*RY - 4 .. ly*RY + RY + 3 of this column,
@@ -528,6 +560,16 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
                     ycol[j] = q[(s + 4) % QS][j - 4];
                 else
                     ycol[j] = L[(ly * RY + j) * LW + lx + 1];
+            }
+            f4 ycol2[FUS ? RY + 8 : 1];
+            if constexpr (FUS) {
+#pragma unroll
+                for (int j = 0; j < RY + 8; ++j) {
+                    if (j >= 4 && j < 4 + RY)
+                        ycol2[j] = q2[(s + 4) % QS][j - 4];
+                    else
+                        ycol2[j] = L2[(ly * RY + j) * LW + lx + 1];
+                }
             }
 
             const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.out, pbytes, z);
@@ -543,7 +585,19 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
                     xs[4 + e] = ctr.v[e];
                     xs[8 + e] = xr.v[e];
                 }
-                f4 out;
+                float xs2[FUS ? 12 : 1];
+                if constexpr (FUS) {
+                    const f4 xl2 = L2[(4 + ly * RY + r) * LW + lx];
+                    const f4 xr2 = L2[(4 + ly * RY + r) * LW + lx + 2];
+                    const f4 ctr2 = q2[(s + 4) % QS][r];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        xs2[e] = xl2.v[e];
+                        xs2[4 + e] = ctr2.v[e];
+                        xs2[8 + e] = xr2.v[e];
+                    }
+                }
+                f4 out, img;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     float lap;
@@ -573,11 +627,28 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
                     }
                     const float g = gxv.v[e] * gyv[r] * gzv[cur_set];
                     if constexpr (IMG) {
-                        // imaging term: (phi / k) G lap a
-                        out.v[e] = pv[cur_set][r].v[e] / kv[cur_set][r].v[e] * g * lap;
+                        // imaging term (G phi / k) lap a
+                        out.v[e] = (g * pv[cur_set][r].v[e]) / kv[cur_set][r].v[e] * lap;
                     } else if constexpr (ADJ) {
                         const float t = fmaf(kv[cur_set][r].v[e], lap, 2.f * ctr.v[e]);
                         out.v[e] = fmaf(-g * g, pv[cur_set][r].v[e], t);
+                        if constexpr (FUS) {
+                            // imaging term of the step after this one: the
+                            // centre already holds G phi, bit for bit g * phi
+                            const float u2b = 2.f * xs2[4 + e];
+                            float lap2 = 0.f;
+#pragma unroll
+                            for (int m = 1; m <= 4; ++m) {
+                                lap2 = fmaf(c.cx[m - 1], (xs2[4 + e + m] + xs2[4 + e - m]) - u2b, lap2);
+                                lap2 = fmaf(c.cy[m - 1],
+                                            (ycol2[4 + r + m].v[e] + ycol2[4 + r - m].v[e]) - u2b, lap2);
+                                lap2 = fmaf(c.cz[m - 1],
+                                            (q2[(s + 4 + m) % QS][r].v[e] + q2[(s + 4 - m + QS) % QS][r].v[e]) -
+                                                u2b,
+                                            lap2);
+                            }
+                            img.v[e] = ctr.v[e] / kv[cur_set][r].v[e] * lap2;
+                        }
                     } else {
                         float t, pe;
                         if constexpr (SCALED) {
@@ -591,18 +662,18 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
                         out.v[e] = g * t;
                     }
                 }
-                if constexpr (IMG) {
-                    // the accumulator has the field layout with 8-byte cells,
-                    // so a full 4-cell group is two aligned 16-byte pairs
+                // the accumulator has the field layout with 8-byte cells, so
+                // a full 4-cell group is two aligned 16-byte pairs
+                auto add_grad = [&](const f4 &t) __attribute__((always_inline)) {
                     if (col_full) {
                         double2 *gp = reinterpret_cast<double2 *>(
                             a.grad + (long long)(z + kGhost) * a.plane + own_in[r] / EB);
                         if (row_int[r]) {
                             double2 g0 = gp[0], g1 = gp[1];
-                            g0.x += (double)out.v[0];
-                            g0.y += (double)out.v[1];
-                            g1.x += (double)out.v[2];
-                            g1.y += (double)out.v[3];
+                            g0.x += (double)t.v[0];
+                            g0.y += (double)t.v[1];
+                            g1.x += (double)t.v[2];
+                            g1.y += (double)t.v[3];
                             gp[0] = g0;
                             gp[1] = g1;
                         }
@@ -611,10 +682,15 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
                             if (x + e < a.nx)
-                                gp[e] += (double)out.v[e];
+                                gp[e] += (double)t.v[e];
                     }
+                };
+                if constexpr (IMG) {
+                    add_grad(out);
                     continue;
                 }
+                if constexpr (FUS)
+                    add_grad(img);
                 if (src_r == r && z == a.src_z) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e)

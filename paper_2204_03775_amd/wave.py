@@ -78,6 +78,7 @@ def _load():
         "wave_destroy": ([vp], ci),
         "wave_forward_checkpointed": ([vp, i32, vp, i32], ci),
         "wave_adjoint": ([vp, vp, vp, i32], ci),
+        "wave_set_adjoint_fusion": ([vp, i32], ci),
         "wave_grad_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                             ctypes.POINTER(i64)], ci),
         "wave_misfit": ([vp, vp, i64, vp, vp, vp], ci),
@@ -209,6 +210,10 @@ def wave_forward_checkpointed(ctx, nt: int, src_ptr=None, every: int = 0):
 
 def wave_adjoint(ctx, trace_grad_ptr, grad_ptr, accumulate: bool = False):
     _check(_lib.wave_adjoint(ctx, trace_grad_ptr, grad_ptr, int(bool(accumulate))), ctx)
+
+
+def wave_set_adjoint_fusion(ctx, on: bool):
+    _check(_lib.wave_set_adjoint_fusion(ctx, int(bool(on))), ctx)
 
 
 def wave_grad_info(ctx):

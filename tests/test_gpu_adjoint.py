@@ -5,8 +5,9 @@ Exact checks:
   - the checkpointed forward run leaves fields and traces bit for bit as a
     plain run does (same kernels, same arithmetic);
   - the gradient does not depend, bit for bit, on the checkpoint interval
-    (recomputed levels equal the first run's) nor on the tile shape (every
-    cell's arithmetic and the order of the sum over steps are fixed);
+    (recomputed levels equal the first run's), on the tile shape (every
+    cell's arithmetic and the order of the sum over steps are fixed), nor
+    on whether the adjoint step and the imaging term share one pass;
   - the misfit residual is traces - observed exactly, the FP64 misfit is
     the FP64 sum of its squares up to summation order.
 Accuracy against the oracle (relative L2 of the gradient):
@@ -123,6 +124,26 @@ def test_gradient_independent_of_tiling(wave_mod, ragged, ragged_tg):
         print(f"case: adjoint {p.name}, variant {wave_mod.wave_variant_name(v)}", flush=True)
         got, _ = gpu_gradient(wave_mod, p, ragged_tg, 9, variant=v)
         assert np.array_equal(got, ref), v
+
+
+@pytest.mark.parametrize("variant", ["auto", "t64x16_r1", "t256x8_r1", "t128x32_r4"])
+def test_fused_and_separate_passes_agree(wave_mod, ragged, ragged_tg, variant):
+    # one pass (adjoint step + imaging term of the next step) and two passes
+    # evaluate the same FP32 operations: equal bit for bit
+    p = ragged
+    tg = torch.tensor(ragged_tg, dtype=torch.float32, device="cuda")
+    out = []
+    for fused in (True, False):
+        print(f"case: adjoint {p.name}, variant {variant}, fused {fused}", flush=True)
+        prop = make_prop(wave_mod, p, wave_mod.variants()[variant])
+        wave_mod.wave_set_adjoint_fusion(prop.ctx, fused)
+        prop.forward_checkpointed(p.nt, src_of(p), 7)
+        g = prop.adjoint(tg)
+        prop.sync()
+        out.append(g.cpu().numpy())
+        prop.close()
+    assert np.array_equal(out[0], out[1])
+    assert np.abs(out[0]).max() > 0
 
 
 def test_adjoint_accumulates_and_repeats(wave_mod, ragged, ragged_tg):
