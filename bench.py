@@ -15,10 +15,11 @@ HBM before timing starts.  The JSON line on stdout carries:
              rocprofv3 counters (profiles/), reported only while the kernel
              source matches the one profiled;
   cpu_baseline  the FP64 CPU oracle on the first steps of the same shot;
-  forms      the FP16 and BF16 storage forms (FP32 arithmetic) on the same
-             shot: throughput, speedup over FP32 and HBM fraction at their 8
-             algorithmic bytes per update, with the accuracy of all three
-             storage types against the FP64 oracle on a 128^3 crop of the
+  forms      the 16-bit storage forms (FP32 arithmetic) on the same shot:
+             FP16 and BF16 holding two time levels (8 algorithmic bytes per
+             update) or u and its step change (10 bytes): throughput,
+             speedup over FP32 and HBM fraction, with the accuracy of every
+             storage type against the FP64 oracle on a 128^3 crop of the
              same model (500 steps);
   batched    32 uneven shots (96..320 x 96..320 x 96..256, 600 steps each,
              FP32) as one autotuned batch replayed from a HIP graph: shots/s
@@ -159,7 +160,7 @@ def crop_accuracy(threads):
                      sponge_alpha=p.sponge_alpha, nthreads=threads)
     s = torch.tensor(p.s, dtype=torch.float32, device="cuda")
     out = {}
-    for dt in ("f32", "f16", "bf16"):
+    for dt in ("f32", "f16", "bf16", "f16uv", "bf16uv"):
         prop = wave.Propagator(p.nx, p.ny, p.nz, p.h, p.k32(), src=p.src, rec=p.rec,
                                sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha, dtype=dt)
         prop.record(p.nt)
@@ -436,7 +437,8 @@ def main() -> int:
     if not args.no_forms and args.workload == "large_shot":
         prop.close()
         forms = {}
-        for dt in ("f16", "bf16"):
+        for dt in ("f16", "bf16", "f16uv", "bf16uv"):
+            bpp = metrics.BYTES_PER_POINT_16UV if dt.endswith("uv") else metrics.BYTES_PER_POINT_16
             pr = wave.Propagator(p.nx, p.ny, p.nz, p.h, p.k32(), src=p.src, rec=p.rec,
                                  sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha, dtype=dt)
             pr.configure(args.variant, args.zchunk)
@@ -448,15 +450,15 @@ def main() -> int:
                 return 1
             pr.close()
             g16 = metrics.gpts_per_s(p.nx, p.ny, p.nz, p.nt * args.steps, w16)
-            a16 = metrics.BYTES_PER_POINT_16 * p.points / k16 / 1e9
+            a16 = bpp * p.points / k16 / 1e9
             forms[dt] = {"value": round(g16, 3), "unit": "Gpts/s", "speedup_vs_f32": round(g16 / gpts, 3),
                          "kernel": wave.wave_variant_name(v16), "zchunk": zc16,
                          "roofline": {"bound": "hbm", "achieved": round(a16, 1),
                                       "peak": metrics.MI355X_HBM_PEAK_GBS, "unit": "GB/s",
                                       "frac": round(a16 / metrics.MI355X_HBM_PEAK_GBS, 4),
-                                      "bytes_per_point": metrics.BYTES_PER_POINT_16}}
+                                      "bytes_per_point": bpp}}
             log(f"{dt}: {g16:.1f} Gpts/s ({g16 / gpts:.2f}x FP32), kernel {k16 * 1e6:.1f} us = "
-                f"{a16:.0f} GB/s at 8 B/pt")
+                f"{a16:.0f} GB/s at {bpp} B/pt")
         acc = crop_accuracy(len(os.sched_getaffinity(0)))
         for dt, a in acc.items():
             a["workload"] = "128^3 crop of the large-shot model, own 20-cell sponge, 500 steps"

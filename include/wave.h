@@ -56,10 +56,21 @@ extern "C" {
 /* storage types: FP32, or 16-bit with FP32 arithmetic.  A 16-bit field
  * holds x * 2^-e with one exponent e per time level, chosen on the device
  * each step from the previous maxima so that |x| * 2^-e < 2^14; k is kept
- * by the library in the same format with a fixed exponent. */
+ * by the library in the same format with a fixed exponent.
+ *   WAVE_F16, WAVE_BF16        the two time levels u^n, u^{n-1} (8 bytes
+ *                              of traffic per cell and step);
+ *   WAVE_F16_UV, WAVE_BF16_UV  u^n and the step change d^n = u^n - u^{n-1}
+ *                              (10 bytes per cell and step).  d is stored
+ *                              to its own relative precision instead of as
+ *                              the difference of two rounded levels, which
+ *                              at small Courant numbers is several times
+ *                              (FP16) to ten times (BF16) more accurate.  The
+ *                              library keeps d in a buffer of its own. */
 #define WAVE_F32 0
 #define WAVE_F16 1
 #define WAVE_BF16 2
+#define WAVE_F16_UV 3
+#define WAVE_BF16_UV 4
 
 typedef struct wave_layout_t {
     int64_t pitch_x;  /* elements per row (a multiple of 128 bytes) */
@@ -76,7 +87,7 @@ typedef struct wave_params_t {
     double dx, dy, dz;    /* grid spacing (> 0), same unit as V dt */
     int32_t sponge_width; /* W >= 0 cells on every face; 0 = no sponge */
     double sponge_alpha;  /* g(d) = exp(-(alpha (W - d))^2) for distance d < W */
-    int32_t dtype;        /* WAVE_F32, WAVE_F16 or WAVE_BF16 */
+    int32_t dtype;        /* WAVE_F32, WAVE_F16, WAVE_BF16, WAVE_F16_UV or WAVE_BF16_UV */
 } wave_params_t;
 
 typedef struct wave_ctx wave_ctx;
@@ -131,13 +142,16 @@ int wave_run(wave_ctx *ctx, int32_t nsteps, const float *src_dev);
  * output pointer may be NULL. */
 int wave_fields(const wave_ctx *ctx, void **cur, void **prev, int64_t *step);
 
-/* Decode u^n (which = 0) or u^{n-1} (which = 1) into dst, an FP32 field in
+/* Decode u^n (which = 0) or u^{n-1} (which = 1, the level stored by the
+ * step before; u-and-change storage keeps it too, though its steps read
+ * d^n instead) into dst, an FP32 field in
  * the FP32 layout (interior written, ghosts untouched); enqueued on the
  * context's stream.  With FP32 storage this is a copy. */
 int wave_export(wave_ctx *ctx, int32_t which, float *dst);
 
 /* Reset the counter to 0 and the roles to those given at init, and clear
- * the 16-bit scale history (the caller re-initialises the field contents). */
+ * the 16-bit scale history and (u-and-change storage) the library's d
+ * field; the caller re-initialises the contents of its own fields. */
 int wave_reset(wave_ctx *ctx);
 
 /* Replace the stream used by later calls. */
@@ -225,7 +239,7 @@ int wave_misfit(const float *traces_dev, const float *observed_dev, int64_t n, f
  * Shots may differ in size, model, source, receivers and tile choice.
  *   ctxs       nshots distinct contexts, configured (wave_configure) before
  *              the batch is created and not reconfigured afterwards; the
- *              naive kernel is not batched;
+ *              naive kernel and u-and-change storage are not batched;
  *   stream     the stream of every batched run (the contexts' own streams
  *              are not used by it); required when use_graph != 0, and then
  *              it must not be the legacy default stream;

@@ -28,22 +28,23 @@ typedef void (*BatchKernel)(const ShotDesc *, BatchItems, int);
 
 struct Variant {
     const char *name;
-    StepKernel fn[3];  // by storage type; all NULL for "auto" and "naive"
-    BatchKernel batch[3];
+    StepKernel fn[kNumKinds];  // by storage type; all NULL for "auto" and "naive"
+    BatchKernel batch[3];      // FP32, FP16, BF16 (two-level storage)
     StepKernel adj[3];  // adjoint step, imaging step, fused adjoint + imaging (FP32)
     int txv, ty, ry;
 };
 
 #define TILED(TXV, TY, RY)                                                                        \
     {step_tiled<WAVE_F32, TXV, TY, RY>, step_tiled<WAVE_F16, TXV, TY, RY>,                        \
-     step_tiled<WAVE_BF16, TXV, TY, RY>},                                                         \
+     step_tiled<WAVE_BF16, TXV, TY, RY>, step_tiled<WAVE_F16_UV, TXV, TY, RY>,                    \
+     step_tiled<WAVE_BF16_UV, TXV, TY, RY>},                                                      \
     {step_batch<WAVE_F32, TXV, TY, RY>, step_batch<WAVE_F16, TXV, TY, RY>,                        \
      step_batch<WAVE_BF16, TXV, TY, RY>},                                                         \
     {adjoint_tiled<kAdj, TXV, TY, RY>, adjoint_tiled<kImg, TXV, TY, RY>, adjoint_tiled<kFus, TXV, TY, RY>}
 
 const Variant kVariants[] = {
-    {"auto", {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, 0, 0, 0},
-    {"naive", {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, 0, 0, 0},
+    {"auto", {nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, 0, 0, 0},
+    {"naive", {nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, 0, 0, 0},
     {"t64x16_r1", TILED(16, 16, 1), 16, 16, 1},
     {"t128x8_r1", TILED(32, 8, 1), 32, 8, 1},
     {"t128x16_r2", TILED(32, 8, 2), 32, 8, 2},
@@ -60,7 +61,12 @@ const Variant kVariants[] = {
 #undef TILED
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kNaive = 1;
-const StepKernel kNaiveFn[3] = {step_naive<WAVE_F32>, step_naive<WAVE_F16>, step_naive<WAVE_BF16>};
+const StepKernel kNaiveFn[kNumKinds] = {step_naive<WAVE_F32>, step_naive<WAVE_F16>, step_naive<WAVE_BF16>,
+                                        step_naive<WAVE_F16_UV>, step_naive<WAVE_BF16_UV>};
+
+// The element encoding of a storage type (the u-and-change types store
+// both of their fields in the encoding of their base type).
+int base_kind(int kind) { return kind == WAVE_F16_UV ? WAVE_F16 : kind == WAVE_BF16_UV ? WAVE_BF16 : kind; }
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -103,6 +109,7 @@ struct wave_ctx {
     void *k16 = nullptr;      // library-owned 16-bit k
     float k_scale = 1.f;
     void *buf0 = nullptr, *buf1 = nullptr;  // roles at init: cur, prev
+    void *dbuf = nullptr;                   // d^n (u-and-change storage), library-owned
     void *cur = nullptr, *prev = nullptr;
     int64_t step = 0;
     int src[3] = {-1, -1, -1};
@@ -164,24 +171,33 @@ void sponge_profile(int n, int width, double alpha, std::vector<float> &g)
 }
 
 // Choose a variant and z-chunk; fill the grid geometry.  Measured on the
-// 512^3 workload: 512-thread work-groups with one float4 per thread, about
-// one per CU (z split into as many chunks as that takes), beat both smaller
-// work-groups and more of them; 256 x 8 tiles edge out 128 x 16 and 64 x 32
-// by about 1.5%.  Every chunk re-reads 8 planes of u^n, so chunks are kept
-// at >= 32 planes.
-constexpr int kAutoVariant = 10;    // t256x8_r1
-constexpr int kSmallVariant = 2;    // t64x16_r1 for grids of fewer than 2^22 cells
+// 512^3 workload:
+//   - FP32: 512-thread work-groups with one float4 per thread, about one
+//     per CU (z split into as many chunks as that takes), beat both smaller
+//     work-groups and more of them; 256 x 8 tiles edge out 128 x 16 and
+//     64 x 32 by about 1.5%;
+//   - 16-bit storage moves half the bytes per load, so a thread needs two
+//     rows to keep enough bytes in flight: 128 x 32 tiles of two rows per
+//     thread at 256 work-groups run 594 Gpts/s against 482 for 256 x 8;
+//   - u-and-change storage (five streams) does best with 128 x 16 tiles of
+//     two rows per thread at 512 work-groups (478 against 361).
+// Every chunk re-reads 8 planes of u^n, so chunks are kept at >= 32 planes.
+constexpr int kAutoVariant = 10;     // t256x8_r1 (FP32)
+constexpr int kAuto16Variant = 12;   // t128x32_r2 (FP16 / BF16, two levels)
+constexpr int kAutoUvVariant = 4;    // t128x16_r2 (u-and-change storage)
+constexpr int kSmallVariant = 2;     // t64x16_r1 for grids of fewer than 2^22 cells
 constexpr int kTargetWorkgroups = 256;
+constexpr int kTargetWorkgroupsUv = 512;
 constexpr int kMinChunk = 32;
 
-Geo plan_geo(int nx, int ny, int nz, int variant, int zchunk)
+Geo plan_geo(int nx, int ny, int nz, int kind, int variant, int zchunk)
 {
     Geo g;
     int v = variant;
-    if (v == 0) {
-        const long long pts = (long long)nx * ny * nz;
-        v = pts >= (1ll << 22) ? kAutoVariant : kSmallVariant;
-    }
+    const bool large = (long long)nx * ny * nz >= (1ll << 22);
+    if (v == 0)
+        v = !large ? kSmallVariant : kind == WAVE_F32 ? kAutoVariant : is_uv(kind) ? kAutoUvVariant : kAuto16Variant;
+    const long long target = large && is_uv(kind) ? kTargetWorkgroupsUv : kTargetWorkgroups;
     g.v = v;
     if (v == kNaive) {
         g.ntx = g.nty = g.nchunks = 0;
@@ -197,7 +213,7 @@ Geo plan_geo(int nx, int ny, int nz, int variant, int zchunk)
     const long long tiles = (long long)g.ntx * g.nty;
     int zc = zchunk;
     if (zc <= 0) {
-        const long long chunks = std::max(1ll, (kTargetWorkgroups + tiles / 2) / tiles);
+        const long long chunks = std::max(1ll, (target + tiles / 2) / tiles);
         zc = int((nz + chunks - 1) / chunks);
         zc = std::max(zc, std::min(kMinChunk, nz));
     }
@@ -212,7 +228,7 @@ Geo plan_geo(int nx, int ny, int nz, int variant, int zchunk)
 
 void plan_launch(wave_ctx *c)
 {
-    const Geo g = plan_geo(c->p.nx, c->p.ny, c->p.nz, c->variant, c->zchunk);
+    const Geo g = plan_geo(c->p.nx, c->p.ny, c->p.nz, c->p.dtype, c->variant, c->zchunk);
     c->v_used = g.v;
     c->ntx = g.ntx;
     c->nty = g.nty;
@@ -309,6 +325,7 @@ StepArgs make_args(const wave_ctx *c)
     a.out = c->prev;
     a.grad = nullptr;
     a.aux = nullptr;
+    a.dlt = c->dbuf;
     return a;
 }
 
@@ -335,10 +352,11 @@ int enqueue_forward(wave_ctx *c, void *cur, void *prev, void *out, const float *
             const void *f = out;
             const long long *off = c->rec_off_all;
             const int *ex = c->ring;
-            if (kind == WAVE_F32)
+            const int bk = base_kind(kind);
+            if (bk == WAVE_F32)
                 hipLaunchKernelGGL(sample_naive<WAVE_F32>, g, b, 0, c->stream, f, off, c->nrec,
                                    a.trace_row, ex, slot);
-            else if (kind == WAVE_F16)
+            else if (bk == WAVE_F16)
                 hipLaunchKernelGGL(sample_naive<WAVE_F16>, g, b, 0, c->stream, f, off, c->nrec,
                                    a.trace_row, ex, slot);
             else
@@ -407,12 +425,15 @@ void free_device(wave_ctx *c)
     free_dev(c->rec_idx);
     free_dev(c->ring);
     free_dev(c->k16);
+    free_dev(c->dbuf);
 }
 
 int launch_convert(hipStream_t s, int src_kind, int dst_kind, const void *src, void *dst, int nx, int ny,
                    int nz, const wave_layout_t &sl, const wave_layout_t &dl, float scale,
                    const int *exps, int slot)
 {
+    src_kind = base_kind(src_kind);
+    dst_kind = base_kind(dst_kind);
     const long long n = (long long)nx * ny * nz;
     const dim3 g((unsigned)std::min<long long>((n + 255) / 256, 8192)), b(256);
     const int spx = int(sl.pitch_x), sx0 = int(sl.x_offset), dpx = int(dl.pitch_x),
@@ -464,7 +485,8 @@ Geo adjoint_geo(const wave_ctx *c)
     if (c->variant != 0 && c->v_used != kNaive)
         return ctx_geo(c);
     const long long pts = (long long)c->p.nx * c->p.ny * c->p.nz;
-    return plan_geo(c->p.nx, c->p.ny, c->p.nz, pts >= (1ll << 22) ? kAdjointAutoVariant : kSmallVariant, 0);
+    return plan_geo(c->p.nx, c->p.ny, c->p.nz, WAVE_F32, pts >= (1ll << 22) ? kAdjointAutoVariant : kSmallVariant,
+                    0);
 }
 
 int enqueue_adjoint(wave_ctx *c, const Geo &geo, int mode, const void *cur, void *nxt, void *out,
@@ -648,7 +670,7 @@ int wave_layout(int32_t nx, int32_t ny, int32_t nz, int32_t dtype, wave_layout_t
 {
     if (!out || nx < 1 || ny < 1 || nz < 1)
         return WAVE_EINVAL;
-    if (dtype != WAVE_F32 && dtype != WAVE_F16 && dtype != WAVE_BF16)
+    if (dtype < WAVE_F32 || dtype >= kNumKinds)
         return WAVE_EINVAL;
     const int64_t eb = elem_bytes(dtype);
     const int64_t align = kRowAlignBytes / eb;
@@ -802,6 +824,14 @@ int wave_init(wave_ctx **out, const wave_params_t *p, const void *k, void *u_cur
             return bail(WAVE_EHIP);
         c->k = c->k16;
     }
+    // u-and-change storage: d^0 = u^0 - u^{-1} = 0 (both start at zero)
+    if (is_uv(p->dtype)) {
+        if (hipMalloc(&c->dbuf, lay.bytes) != hipSuccess)
+            return bail(WAVE_ENOMEM);
+        if (hipMemsetAsync(c->dbuf, 0, lay.bytes, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return bail(WAVE_EHIP);
+    }
 
     *out = c;
     return WAVE_OK;
@@ -881,6 +911,8 @@ int wave_reset(wave_ctx *ctx)
     ctx->prev = ctx->buf1;
     ctx->step = 0;
     HIP_TRY(ctx, hipMemsetAsync(ctx->ring, 0, 8 * sizeof(int), ctx->stream));
+    if (ctx->dbuf)
+        HIP_TRY(ctx, hipMemsetAsync(ctx->dbuf, 0, ctx->lay.bytes, ctx->stream));
     return WAVE_OK;
 }
 
@@ -1162,7 +1194,7 @@ int wave_batch_create(wave_batch **out, wave_ctx *const *ctxs, int32_t nshots, v
     if (!ctxs || nshots < 1 || (use_graph && !stream))
         return WAVE_EINVAL;
     for (int i = 0; i < nshots; ++i) {
-        if (!ctxs[i] || ctxs[i]->v_used == kNaive)
+        if (!ctxs[i] || ctxs[i]->v_used == kNaive || is_uv(ctxs[i]->p.dtype))
             return WAVE_EINVAL;
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i])

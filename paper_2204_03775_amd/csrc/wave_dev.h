@@ -24,6 +24,8 @@ constexpr double kSymbolMax = 2048.0 / 315.0;
 constexpr int kScaledTopExp = 14;
 
 constexpr int elem_bytes(int dtype) { return dtype == WAVE_F32 ? 4 : 2; }
+constexpr int kNumKinds = 5;  // storage types WAVE_F32 .. WAVE_BF16_UV
+constexpr bool is_uv(int dtype) { return dtype == WAVE_F16_UV || dtype == WAVE_BF16_UV; }
 
 struct alignas(16) f4 {
     float v[4];
@@ -69,6 +71,8 @@ struct StepArgs {
     double *grad;
     // fused adjoint step: the forward level whose Laplacian the imaging term needs
     const void *aux;
+    // u-and-change storage: d^n on entry, d^{n+1} on exit (same cells, same thread)
+    void *dlt;
 };
 
 // What a tiled launch computes (FP32 storage only for the last two):

@@ -69,11 +69,13 @@ struct Store;
 template <>
 struct Store<WAVE_F32> {
     static constexpr bool scaled = false;
+    static constexpr bool uv = false;
     static constexpr unsigned bytes = 4;
 };
 template <>
 struct Store<WAVE_F16> {
     static constexpr bool scaled = true;
+    static constexpr bool uv = false;
     static constexpr unsigned bytes = 2;
     static __device__ __forceinline__ float dec(unsigned bits)
     {
@@ -87,12 +89,22 @@ struct Store<WAVE_F16> {
 template <>
 struct Store<WAVE_BF16> {
     static constexpr bool scaled = true;
+    static constexpr bool uv = false;
     static constexpr unsigned bytes = 2;
     static __device__ __forceinline__ float dec(unsigned bits) { return __uint_as_float(bits << 16); }
     static __device__ __forceinline__ unsigned enc(float x)
     {
         return __builtin_bit_cast(unsigned short, (__bf16)x);
     }
+};
+// u and its step change d = u^n - u^{n-1}, same 16-bit encodings
+template <>
+struct Store<WAVE_F16_UV> : Store<WAVE_F16> {
+    static constexpr bool uv = true;
+};
+template <>
+struct Store<WAVE_BF16_UV> : Store<WAVE_BF16> {
+    static constexpr bool uv = true;
 };
 
 // Raw buffer access.  A buffer resource covers one plane of one field; any
@@ -195,10 +207,18 @@ struct Scales {
 // a power of two commutes with every FP32 rounding, so this is bit for bit
 // the decode -> compute -> encode sequence, without the per-value
 // multiplies.
+//
+// With u-and-change storage the second input is D, the stored d^n =
+// u^n - u^{n-1} (exponent one above u^n's), and u^{n-1} in output units is
+// A U - B D with B = sc_d / sc_out; the same expression follows.  The new
+// change d^{n+1} = u^{n+1} - u^n is formed in FP32 before either is
+// rounded and stored with the exponent of u^{n+1} plus one (it is bounded
+// by |u^{n+1}| + |u^n| < 2^(e + 15)).
 struct Folded {
     Coefs c;       // weights times C
     float two_a;   // 2 A
     float b;       // B
+    float a;       // A
 };
 
 __device__ __forceinline__ Folded fold_scales(const Coefs &c, const Scales &sc, float k_scale)
@@ -215,9 +235,11 @@ __device__ __forceinline__ Folded fold_scales(const Coefs &c, const Scales &sc, 
     }
     f.two_a = 2.f * A;
     f.b = sc.prev * sc.out_inv;
+    f.a = A;
     return f;
 }
 
+template <int KIND>
 __device__ __forceinline__ Scales step_scales(const StepArgs &a)
 {
     const int n = a.step;
@@ -232,7 +254,8 @@ __device__ __forceinline__ Scales step_scales(const StepArgs &a)
     }
     Scales sc;
     sc.cur = ldexpf(1.f, a.exps[n & 3]);
-    sc.prev = ldexpf(1.f, a.exps[(n + 3) & 3]);
+    // second input: u^{n-1}, or d^n (exponent of u^n plus one)
+    sc.prev = Store<KIND>::uv ? ldexpf(1.f, a.exps[n & 3] + 1) : ldexpf(1.f, a.exps[(n + 3) & 3]);
     sc.out = ldexpf(1.f, e);
     sc.out_inv = ldexpf(1.f, -e);
     sc.e_out = e;
@@ -306,6 +329,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
     constexpr int QS = 10;                   // queue slots: 9 live planes + 1 being filled
     constexpr unsigned EB = Store<KIND>::bytes;
     constexpr bool SCALED = Store<KIND>::scaled;
+    constexpr bool UV = Store<KIND>::uv;          // second input is d^n, also written
     constexpr bool FUS = MODE == kFus;            // adjoint step + imaging term of the step after it
     constexpr bool ADJ = MODE == kAdj || FUS;     // the stencil field is phi, scaled by G on load
     constexpr bool IMG = MODE == kImg;
@@ -330,9 +354,9 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
     const int x = 4 * xq;
 
     Scales sc{1.f, 1.f, 1.f, 1.f, 0};
-    Folded fd{a.c, 2.f, 1.f};
+    Folded fd{a.c, 2.f, 1.f, 1.f};
     if constexpr (SCALED) {
-        sc = step_scales(a);
+        sc = step_scales<KIND>(a);
         publish_scale(a, sc, lid, tid);
         fd = fold_scales(a.c, sc, a.k_scale);
     }
@@ -476,7 +500,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
     float gzv[2], gzq[2];  // g_z of the plane and (adjoint) of the queue plane z + 4
     auto prefetch = [&](int z, int slot, int set) {
         const __amdgpu_buffer_rsrc_t rq = plane_rsrc(a.cur, pbytes, z + 4);
-        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(a.nxt, pbytes, z);
+        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(UV ? a.dlt : a.nxt, pbytes, z);
         const __amdgpu_buffer_rsrc_t rk = plane_rsrc(a.k, pbytes, z);
         const __amdgpu_buffer_rsrc_t rh = plane_rsrc(a.cur, pbytes, z);
 #pragma unroll
@@ -573,6 +597,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
             }
 
             const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.out, pbytes, z);
+            const __amdgpu_buffer_rsrc_t rdl = plane_rsrc(UV ? a.dlt : a.out, pbytes, z);
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
                 const f4 xl = L[(4 + ly * RY + r) * LW + lx];
@@ -653,7 +678,10 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
                         float t, pe;
                         if constexpr (SCALED) {
                             t = fmaf(kv[cur_set][r].v[e], lap, fd.two_a * ctr.v[e]);
-                            pe = fd.b * pv[cur_set][r].v[e];
+                            if constexpr (UV)  // u^{n-1} = u^n - d^n
+                                pe = fmaf(-fd.b, pv[cur_set][r].v[e], fd.a * ctr.v[e]);
+                            else
+                                pe = fd.b * pv[cur_set][r].v[e];
                         } else {
                             t = fmaf(kv[cur_set][r].v[e], lap, 2.f * ctr.v[e]);
                             pe = pv[cur_set][r].v[e];
@@ -697,8 +725,16 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
                         if (e == src_e)
                             out.v[e] += sval;
                 }
+                f4 dn;  // d^{n+1} in its own units (u-and-change storage)
+                if constexpr (UV) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        dn.v[e] = 0.5f * (out.v[e] - fd.a * ctr.v[e]);
+                }
                 if (col_full) {
                     store4<KIND>(ro, own_in[r], out, 1.f);
+                    if constexpr (UV)
+                        store4<KIND>(rdl, own_in[r], dn, 1.f);
                     if constexpr (SCALED) {
                         if (row_int[r]) {
 #pragma unroll
@@ -711,6 +747,8 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
                     for (int e = 0; e < 4; ++e) {
                         const bool in = x + e < a.nx;
                         store1<KIND>(ro, in ? own_in[r] + EB * e : kOff, out.v[e], 1.f);
+                        if constexpr (UV)
+                            store1<KIND>(rdl, in ? own_in[r] + EB * e : kOff, dn.v[e], 1.f);
                         if constexpr (SCALED)
                             tmax = in ? fmaxf(tmax, fabsf(out.v[e])) : tmax;
                     }
@@ -803,9 +841,9 @@ __global__ __launch_bounds__(256) void step_naive(StepArgs a)
 {
     constexpr bool SCALED = Store<KIND>::scaled;
     Scales sc{1.f, 1.f, 1.f, 1.f, 0};
-    Folded fd{a.c, 2.f, 1.f};
+    Folded fd{a.c, 2.f, 1.f, 1.f};
     if constexpr (SCALED) {
-        sc = step_scales(a);
+        sc = step_scales<KIND>(a);
         publish_scale(a, sc, blockIdx.x, threadIdx.x);
         fd = fold_scales(a.c, sc, a.k_scale);
     }
@@ -831,11 +869,14 @@ __global__ __launch_bounds__(256) void step_naive(StepArgs a)
         }
         const float g = a.gx[x] * a.gy[y] * a.gz[z];
         const float kk = read_elem<KIND>(a.k, p, 1.f);
-        const float pp = read_elem<KIND>(a.nxt, p, 1.f);
+        const float pp = read_elem<KIND>(Store<KIND>::uv ? a.dlt : a.nxt, p, 1.f);
         float t, pe;
         if constexpr (SCALED) {
             t = fmaf(kk, lap, fd.two_a * u);
-            pe = fd.b * pp;
+            if constexpr (Store<KIND>::uv)
+                pe = fmaf(-fd.b, pp, fd.a * u);
+            else
+                pe = fd.b * pp;
         } else {
             t = fmaf(kk, lap, 2.f * u);
             pe = pp;
@@ -848,6 +889,9 @@ __global__ __launch_bounds__(256) void step_naive(StepArgs a)
             static_cast<float *>(a.out)[p] = v;
         } else {
             static_cast<unsigned short *>(a.out)[p] = (unsigned short)Store<KIND>::enc(v);
+            if constexpr (Store<KIND>::uv)
+                static_cast<unsigned short *>(a.dlt)[p] =
+                    (unsigned short)Store<KIND>::enc(0.5f * (v - fd.a * u));
             amax = fabsf(v);
         }
     }

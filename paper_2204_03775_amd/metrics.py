@@ -14,6 +14,7 @@ from __future__ import annotations
 PAPER_FLOP_PER_CELL = 51
 BYTES_PER_POINT_F32 = 16
 BYTES_PER_POINT_16 = 8  # FP16 / BF16 storage of u^n, u^{n-1}, k and u^{n+1}
+BYTES_PER_POINT_16UV = 10  # 16-bit u^n, d^n, k read; u^{n+1}, d^{n+1} written
 MI355X_HBM_PEAK_GBS = 8000.0  # published HBM3E bandwidth, GB/s
 
 

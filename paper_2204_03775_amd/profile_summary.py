@@ -8,6 +8,9 @@
       --fetch-probe PF --write-probe PW --title T --commands CMDS --out FILE.md
       the same scaling for every library kernel, per kernel and grid size;
 
+  python -m paper_2204_03775_amd.profile_summary counters --csv C --title T --command CMD --out F
+      per-kernel averages of any counter set (LDS bank conflicts, issue);
+
   python -m paper_2204_03775_amd.profile_summary traffic \\
       --fetch-step F --write-step W --fetch-probe PF --write-probe PW \\
       --kernel NAME --zchunk ZC --points N --commands CMDS --out-json J --out-md M
@@ -154,6 +157,33 @@ def kernels(a):
     print("\n".join(lines))
 
 
+def counters(a):
+    """Average of every counter per dispatch, per kernel and grid size, for
+    the library's kernels; with the LDS counters present, the bank-conflict
+    ratio SQ_LDS_BANK_CONFLICT / (SQ_LDS_IDX_ACTIVE - SQ_LDS_BANK_CONFLICT)
+    (conflict cycles per conflict-free LDS cycle)."""
+    d = collections.defaultdict(lambda: collections.defaultdict(list))
+    with open(a.csv) as f:
+        for r in csv.DictReader(f):
+            if a.match in r["Kernel_Name"]:
+                d[(r["Kernel_Name"], int(r["Grid_Size"]))][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    names = sorted({c for v in d.values() for c in v})
+    lines = [f"# {a.title}", "", "Averages per dispatch (counters summed over the GPU).", "",
+             "| kernel | grid | dispatches | " + " | ".join(names) + (" | LDS conflict ratio |" if "SQ_LDS_BANK_CONFLICT" in names else " |"),
+             "|---|---:|---:|" + "---:|" * len(names) + ("---:|" if "SQ_LDS_BANK_CONFLICT" in names else "")]
+    for (name, grid), v in sorted(d.items(), key=lambda kv: kv[0]):
+        av = {c: sum(x) / len(x) for c, x in v.items()}
+        n = max(len(x) for x in v.values())
+        row = f"| `{_short(name, 60)}` | {grid} | {n} | " + " | ".join(f"{av.get(c, 0):.4g}" for c in names)
+        if "SQ_LDS_BANK_CONFLICT" in names:
+            act, bc = av.get("SQ_LDS_IDX_ACTIVE", 0.0), av.get("SQ_LDS_BANK_CONFLICT", 0.0)
+            row += f" | {bc / (act - bc):.4f}" if act > bc else " | -"
+        lines.append(row + " |")
+    lines += ["", "Command:", "", f"    {a.command}"]
+    open(a.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -174,8 +204,14 @@ def main():
     k.add_argument("--match", default="wavek::")
     k.add_argument("--probe-elements", type=int, required=True)
     k.add_argument("--commands", nargs="+", required=True)
+    c = sub.add_parser("counters")
+    for name in ("csv", "out", "title", "command"):
+        c.add_argument("--" + name, required=True)
+    c.add_argument("--match", default="wavek::")
     a = ap.parse_args()
-    if a.cmd == "stats":
+    if a.cmd == "counters":
+        counters(a)
+    elif a.cmd == "stats":
         stats(a.prefix, a.command, a.out)
     elif a.cmd == "kernels":
         kernels(a)

@@ -29,8 +29,12 @@ WAVE_EHIP = -5
 WAVE_F32 = 0
 WAVE_F16 = 1
 WAVE_BF16 = 2
-DTYPES = {"f32": WAVE_F32, "f16": WAVE_F16, "bf16": WAVE_BF16}
-_TORCH_DTYPE = {WAVE_F32: torch.float32, WAVE_F16: torch.float16, WAVE_BF16: torch.bfloat16}
+WAVE_F16_UV = 3
+WAVE_BF16_UV = 4
+DTYPES = {"f32": WAVE_F32, "f16": WAVE_F16, "bf16": WAVE_BF16, "f16uv": WAVE_F16_UV,
+          "bf16uv": WAVE_BF16_UV}
+_TORCH_DTYPE = {WAVE_F32: torch.float32, WAVE_F16: torch.float16, WAVE_BF16: torch.bfloat16,
+                WAVE_F16_UV: torch.float16, WAVE_BF16_UV: torch.bfloat16}
 
 GHOST = 4
 
@@ -283,7 +287,9 @@ class Propagator:
     """Fields in the library's padded layout (torch tensors on the current
     device) plus a context.  ``k`` is a dense [nz][ny][nx] array (numpy or
     torch) of V^2 dt^2, rounded to FP32 once.  ``dtype`` selects the field
-    storage: "f32", or "f16" / "bf16" (16-bit storage, FP32 arithmetic)."""
+    storage: "f32"; "f16" / "bf16" (two 16-bit time levels, FP32
+    arithmetic); "f16uv" / "bf16uv" (16-bit u^n and step change d^n, the
+    latter held by the library)."""
 
     def __init__(self, nx, ny, nz, h, k, *, src=None, rec=None, sponge_width=0,
                  sponge_alpha=0.0, stream=None, device=None, dtype="f32"):

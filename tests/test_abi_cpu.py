@@ -73,7 +73,7 @@ FAKE = 0x7f0000000000
 
 
 @pytest.mark.parametrize("kw", [dict(nx=0), dict(dx=0.0), dict(dy=-1.0), dict(dz=float("nan")),
-                                dict(sponge_width=-1), dict(sponge_alpha=-0.1), dict(dtype=3)])
+                                dict(sponge_width=-1), dict(sponge_alpha=-0.1), dict(dtype=5)])
 def test_init_rejects_bad_params(w, kw):
     with pytest.raises(w.WaveError) as e:
         w.wave_init(_params(w, **kw), FAKE, FAKE + 4096, FAKE + 8192)
