@@ -26,6 +26,8 @@ HBM before timing starts.  The JSON line on stdout carries:
              and aggregate Gpts/s, against the same 32 shots run one after
              another with the library's automatic configuration (their
              traces must agree bit for bit).
+  launch     the 64^3 x 100-step parity shot (launch-bound): eager launches
+             against graph replay of the whole run;
   gradient   the least-squares misfit gradient with respect to k on a 256^3
              layered model with a Gaussian anomaly (800 steps, 128
              receivers): checkpointed forward run (every 50 steps, and with
@@ -368,6 +370,43 @@ def gradient_leg(reps: int, threads: int):
             "repeats": reps}
 
 
+def launch_leg(reps: int):
+    """The 64^3 x 100-step parity shot, launch-bound: eager launches
+    against graph replay (wave_set_graph), ms per shot."""
+    import torch
+
+    from paper_2204_03775_amd import inputs, wave
+
+    p = inputs.small_parity()
+    stream = torch.cuda.Stream()
+    s = torch.tensor(p.s, dtype=torch.float32, device="cuda")
+    prop = wave.Propagator(p.nx, p.ny, p.nz, p.h, p.k32(), src=p.src, rec=p.rec, stream=stream)
+    prop.record(p.nt)
+
+    def timed():
+        with torch.cuda.stream(stream):
+            prop.reset()
+        prop.run(p.nt, s)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            with torch.cuda.stream(stream):
+                prop.reset()
+            prop.run(p.nt, s)
+        stream.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_eager = timed()
+    prop.use_graph(True)
+    t_graph = timed()
+    prop.close()
+    log(f"launch: 64^3 x {p.nt}: eager {t_eager * 1e3:.3f} ms/shot, graph {t_graph * 1e3:.3f} ms/shot")
+    return {"workload": "64^3 x 100 steps FP32 (the parity shot), 16 receivers",
+            "eager_ms_per_shot": round(t_eager * 1e3, 4), "graph_ms_per_shot": round(t_graph * 1e3, 4),
+            "graph_speedup": round(t_eager / t_graph, 3),
+            "graph_gpts_per_s": round(p.points * p.nt / t_graph / 1e9, 3), "repeats": reps}
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -477,6 +516,10 @@ def main() -> int:
             log("error: batched traces differ from the sequential runs")
             return 1
 
+    launch = None
+    if args.workload == "large_shot":
+        launch = launch_leg(20)
+
     gradient = None
     if not args.no_gradient and args.workload == "large_shot":
         prop.close()
@@ -518,6 +561,7 @@ def main() -> int:
         "forms": forms,
         "batched": batched,
         "gradient": gradient,
+        "launch": launch,
     }
     prop.close()
     print(json.dumps(rec), flush=True)

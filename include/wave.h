@@ -138,6 +138,16 @@ int wave_step(wave_ctx *ctx, float src_value);
  * src_dev is NULL. */
 int wave_run(wave_ctx *ctx, int32_t nsteps, const float *src_dev);
 
+/* Graph replay of wave_run (on != 0): a run's launches are captured once as
+ * a HIP graph and replayed by later runs that start from the same state --
+ * same step counter, buffer roles, source array, trace buffer and nsteps,
+ * e.g. the same shot again after wave_reset; any other run is captured
+ * anew (the last capture is kept).  Meant for small grids, where a
+ * launch costs more than the step it runs (the time loop of Algorithm 1 is
+ * one launch per step).  Needs a stream other than the legacy default
+ * stream (WAVE_EINVAL).  Results are bit for bit those of eager launches. */
+int wave_set_graph(wave_ctx *ctx, int32_t on);
+
 /* Current roles: *cur holds u^n and *prev u^{n-1}, with n = *step.  Any
  * output pointer may be NULL. */
 int wave_fields(const wave_ctx *ctx, void **cur, void **prev, int64_t *step);

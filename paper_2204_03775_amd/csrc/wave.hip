@@ -131,6 +131,18 @@ struct wave_ctx {
     int ntx = 0, nty = 0, nchunks = 0, nwg = 0, grid = 0;
     wave_grad_state g;
     bool fuse_adjoint = true;  // adjoint step and imaging term in one pass
+    // graph replay of wave_run: the launches of the last captured run and
+    // the state it started from
+    struct RunGraph {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        int64_t step0 = -1;
+        int nsteps = 0;
+        const float *src = nullptr;
+        float *traces = nullptr;
+        void *cur = nullptr, *prev = nullptr;
+    } rg;
+    bool use_graph = false;
     std::string err;
 };
 
@@ -182,13 +194,19 @@ void sponge_profile(int n, int width, double alpha, std::vector<float> &g)
 //   - u-and-change storage (five streams) does best with 128 x 16 tiles of
 //     two rows per thread at 512 work-groups (478 against 361).
 // Every chunk re-reads 8 planes of u^n, so chunks are kept at >= 32 planes.
+// Grids of fewer than 2^22 cells fit in the caches and are latency-bound:
+// there, about 512 work-groups with chunks down to one plane run 3-6x
+// faster per step than 32-plane chunks (48^3: 3.9 against 24.8 us per
+// step; 128^3: 9.5 against 25.9; 192^3: about 25 against 29).
 constexpr int kAutoVariant = 10;     // t256x8_r1 (FP32)
 constexpr int kAuto16Variant = 12;   // t128x32_r2 (FP16 / BF16, two levels)
 constexpr int kAutoUvVariant = 4;    // t128x16_r2 (u-and-change storage)
 constexpr int kSmallVariant = 2;     // t64x16_r1 for grids of fewer than 2^22 cells
 constexpr int kTargetWorkgroups = 256;
 constexpr int kTargetWorkgroupsUv = 512;
+constexpr int kTargetWorkgroupsSmall = 512;
 constexpr int kMinChunk = 32;
+constexpr int kMinChunkSmall = 1;
 
 Geo plan_geo(int nx, int ny, int nz, int kind, int variant, int zchunk)
 {
@@ -197,7 +215,8 @@ Geo plan_geo(int nx, int ny, int nz, int kind, int variant, int zchunk)
     const bool large = (long long)nx * ny * nz >= (1ll << 22);
     if (v == 0)
         v = !large ? kSmallVariant : kind == WAVE_F32 ? kAutoVariant : is_uv(kind) ? kAutoUvVariant : kAuto16Variant;
-    const long long target = large && is_uv(kind) ? kTargetWorkgroupsUv : kTargetWorkgroups;
+    const long long target = !large ? kTargetWorkgroupsSmall : is_uv(kind) ? kTargetWorkgroupsUv : kTargetWorkgroups;
+    const int min_chunk = large ? kMinChunk : kMinChunkSmall;
     g.v = v;
     if (v == kNaive) {
         g.ntx = g.nty = g.nchunks = 0;
@@ -215,7 +234,7 @@ Geo plan_geo(int nx, int ny, int nz, int kind, int variant, int zchunk)
     if (zc <= 0) {
         const long long chunks = std::max(1ll, (target + tiles / 2) / tiles);
         zc = int((nz + chunks - 1) / chunks);
-        zc = std::max(zc, std::min(kMinChunk, nz));
+        zc = std::max(zc, std::min(min_chunk, nz));
     }
     if (zc > nz)
         zc = nz;
@@ -413,8 +432,18 @@ void free_grad(wave_grad_state &g)
     g = wave_grad_state();
 }
 
+void drop_run_graph(wave_ctx *c)
+{
+    if (c->rg.exec)
+        (void)hipGraphExecDestroy(c->rg.exec);
+    if (c->rg.graph)
+        (void)hipGraphDestroy(c->rg.graph);
+    c->rg = wave_ctx::RunGraph();
+}
+
 void free_device(wave_ctx *c)
 {
+    drop_run_graph(c);
     free_grad(c->g);
     free_dev(c->gx);
     free_dev(c->gy);
@@ -867,11 +896,73 @@ int wave_run(wave_ctx *ctx, int32_t nsteps, const float *src_dev)
     int rc = check_trace_room(ctx, nsteps);
     if (rc != WAVE_OK)
         return rc;
+    if (ctx->use_graph && nsteps > 0) {
+        wave_ctx::RunGraph &g = ctx->rg;
+        const bool same = g.exec && g.step0 == ctx->step && g.nsteps == nsteps && g.src == src_dev &&
+                          g.traces == ctx->traces && g.cur == ctx->cur && g.prev == ctx->prev;
+        if (!same) {
+            // capture this run's launches (the host bookkeeping advances as
+            // in an eager run), then replay them
+            drop_run_graph(ctx);
+            const int64_t step0 = ctx->step;
+            void *cur0 = ctx->cur, *prev0 = ctx->prev;
+            HIP_TRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+            int lrc = WAVE_OK;
+            for (int32_t j = 0; j < nsteps && lrc == WAVE_OK; ++j)
+                lrc = launch_step(ctx, src_dev ? src_dev + j : nullptr, 0.0f);
+            hipGraph_t graph = nullptr;
+            const hipError_t ec = hipStreamEndCapture(ctx->stream, &graph);
+            if (lrc != WAVE_OK || ec != hipSuccess) {
+                if (graph)
+                    (void)hipGraphDestroy(graph);
+                ctx->step = step0;
+                ctx->cur = cur0;
+                ctx->prev = prev0;
+                return lrc != WAVE_OK ? lrc : fail(ctx, WAVE_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+            }
+            hipGraphExec_t exec = nullptr;
+            if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                (void)hipGraphDestroy(graph);
+                ctx->step = step0;
+                ctx->cur = cur0;
+                ctx->prev = prev0;
+                return fail(ctx, WAVE_EHIP, "graph instantiation failed");
+            }
+            g.graph = graph;
+            g.exec = exec;
+            g.step0 = step0;
+            g.nsteps = nsteps;
+            g.src = src_dev;
+            g.traces = ctx->traces;
+            g.cur = cur0;
+            g.prev = prev0;
+            HIP_TRY(ctx, hipGraphLaunch(exec, ctx->stream));
+            return WAVE_OK;
+        }
+        HIP_TRY(ctx, hipGraphLaunch(g.exec, ctx->stream));
+        // the same bookkeeping as the captured launches
+        if (nsteps & 1)
+            std::swap(ctx->cur, ctx->prev);
+        ctx->step += nsteps;
+        return WAVE_OK;
+    }
     for (int32_t j = 0; j < nsteps; ++j) {
         rc = launch_step(ctx, src_dev ? src_dev + j : nullptr, 0.0f);
         if (rc != WAVE_OK)
             return rc;
     }
+    return WAVE_OK;
+}
+
+int wave_set_graph(wave_ctx *ctx, int32_t on)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    if (on && !ctx->stream)
+        return fail(ctx, WAVE_EINVAL, "graph replay needs a stream other than the legacy default stream");
+    ctx->use_graph = on != 0;
+    if (!ctx->use_graph)
+        drop_run_graph(ctx);
     return WAVE_OK;
 }
 
@@ -920,6 +1011,8 @@ int wave_set_stream(wave_ctx *ctx, void *stream)
 {
     if (!ctx)
         return WAVE_EINVAL;
+    if (!stream && ctx->use_graph)
+        return fail(ctx, WAVE_EINVAL, "graph replay is on: the stream cannot be the legacy default stream");
     ctx->stream = static_cast<hipStream_t>(stream);
     return WAVE_OK;
 }
@@ -932,6 +1025,7 @@ int wave_configure(wave_ctx *ctx, int32_t variant, int32_t zchunk)
         return fail(ctx, WAVE_EINVAL, "unknown variant %d or negative z-chunk %d", variant, zchunk);
     ctx->variant = variant;
     ctx->zchunk = zchunk;
+    drop_run_graph(ctx);  // its launches name the old tables
     plan_launch(ctx);
     return build_receiver_tables(ctx);
 }
@@ -1262,6 +1356,24 @@ int wave_batch_create(wave_batch **out, wave_ctx *const *ctxs, int32_t nshots, v
             acc += work[i];
             while (part < 8 && acc >= wsum * part / 8.0)
                 xs[part++] = i + 1;
+        }
+        // within each range, longest items first (stable: the items of one
+        // shot keep their spatial order), so that the end of a step is
+        // made of short items
+        {
+            std::vector<int> order(g.total);
+            for (int i = 0; i < g.total; ++i)
+                order[i] = i;
+            for (int r = 0; r < 8; ++r)
+                std::stable_sort(order.begin() + xs[r], order.begin() + xs[r + 1],
+                                 [&](int a, int b) { return work[a] > work[b]; });
+            std::vector<int> s2(g.total), l2(g.total);
+            for (int i = 0; i < g.total; ++i) {
+                s2[i] = ishot[order[i]];
+                l2[i] = ilid[order[i]];
+            }
+            ishot.swap(s2);
+            ilid.swap(l2);
         }
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, V.batch[g.kind], g.threads, 0) !=

@@ -83,6 +83,7 @@ def _load():
         "wave_forward_checkpointed": ([vp, i32, vp, i32], ci),
         "wave_adjoint": ([vp, vp, vp, i32], ci),
         "wave_set_adjoint_fusion": ([vp, i32], ci),
+        "wave_set_graph": ([vp, i32], ci),
         "wave_grad_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                             ctypes.POINTER(i64)], ci),
         "wave_misfit": ([vp, vp, i64, vp, vp, vp], ci),
@@ -214,6 +215,10 @@ def wave_forward_checkpointed(ctx, nt: int, src_ptr=None, every: int = 0):
 
 def wave_adjoint(ctx, trace_grad_ptr, grad_ptr, accumulate: bool = False):
     _check(_lib.wave_adjoint(ctx, trace_grad_ptr, grad_ptr, int(bool(accumulate))), ctx)
+
+
+def wave_set_graph(ctx, on: bool):
+    _check(_lib.wave_set_graph(ctx, int(bool(on))), ctx)
 
 
 def wave_set_adjoint_fusion(ctx, on: bool):
@@ -405,6 +410,11 @@ class Propagator:
         """(steps, segment length, segments, checkpoint bytes) of the last
         checkpointed run."""
         return wave_grad_info(self.ctx)
+
+    def use_graph(self, on: bool = True):
+        """Replay repeated runs from a captured HIP graph (needs a
+        non-default stream)."""
+        wave_set_graph(self.ctx, on)
 
     def configure(self, variant=0, zchunk=0):
         if isinstance(variant, str):
