@@ -21,7 +21,7 @@ import torch
 from . import wave
 
 VARIANTS = ("t256x8_r1", "t128x16_r1", "t128x8_r1", "t64x16_r1", "t64x32_r1")
-CHUNK_FRACTIONS = (1, 2)  # z split into this many chunks
+CHUNK_FRACTIONS = (1, 2, 4, 8)  # z split into this many chunks
 DEFAULT = ("t256x8_r1", 1)
 
 
