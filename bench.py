@@ -14,11 +14,15 @@ HBM before timing starts.  The JSON line on stdout carries:
              `traffic` is the HBM byte count per launch measured with
              rocprofv3 counters (profiles/), reported only while the kernel
              source matches the one profiled;
-  cpu_baseline  the FP64 CPU oracle on the first steps of the same shot;
+  cpu_baseline  the CPU leg: the FP64 oracle, as it stands, timed on the
+             first steps of the same shot on the host cores.  The same leg
+             runs the oracle's reference results that the accuracy figures
+             of the other legs compare with (the oracle runs in no other
+             leg; without the CPU leg those figures are absent);
   forms      the 16-bit storage forms (FP32 arithmetic) on the same shot:
              FP16 and BF16 holding two time levels (8 algorithmic bytes per
              update) or u and its step change (10 bytes): throughput,
-             speedup over FP32 and HBM fraction, with the accuracy of every
+             speedup over FP32 and HBM fraction, and the accuracy of every
              storage type against the FP64 oracle on a 128^3 crop of the
              same model (500 steps);
   batched    32 uneven shots (96..320 x 96..320 x 96..256, 600 steps each,
@@ -33,8 +37,8 @@ HBM before timing starts.  The JSON line on stdout carries:
              receivers): checkpointed forward run (every 50 steps, and with
              every level kept), FP64 misfit, adjoint run with FP64
              accumulation; time against one FP32 forward run of the same
-             shot, and accuracy and speed against the FP64 oracle's adjoint
-             on a 48^3 crop (300 steps).
+             shot, and, on a 48^3 crop (300 steps), accuracy and speed
+             against the FP64 oracle's adjoint.
 """
 from __future__ import annotations
 
@@ -88,17 +92,23 @@ def measured_traffic(kernel_name: str, zchunk: int):
 
 
 def cpu_baseline(p, target_seconds: float):
-    """The FP64 oracle, as it stands, on the first steps of the same shot."""
+    """The FP64 oracle, as it stands, timed on the first steps of the same
+    shot on the host cores."""
     import oracle
 
     threads = oracle.default_threads()
     k64 = p.k64()
     kw = dict(s=p.s, src=p.src, rec=p.rec, sponge_width=p.sponge_width,
               sponge_alpha=p.sponge_alpha, nthreads=threads)
+    # per-step time from two short runs (their difference removes the set-up)
     t = time.perf_counter()
-    oracle.run(k64, p.h, 3, **kw)
-    per_step = (time.perf_counter() - t) / 3
-    n = int(max(3, min(p.nt, round(target_seconds / max(per_step, 1e-4)))))
+    oracle.run(k64, p.h, 2, **kw)
+    t2 = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.run(k64, p.h, 6, **kw)
+    t6 = time.perf_counter() - t
+    per_step = max((t6 - t2) / 4, t6 / 60, 1e-4)
+    n = int(max(3, min(p.nt, round(target_seconds / per_step))))
     t = time.perf_counter()
     oracle.run(k64, p.h, n, **kw)
     sec = time.perf_counter() - t
@@ -107,6 +117,55 @@ def cpu_baseline(p, target_seconds: float):
             "sample": f"first {n} of the {p.nt} steps of the same {p.nx}x{p.ny}x{p.nz} shot, "
                       f"FP64, {sec:.1f} s, OpenMP threads={threads}, "
                       f"cpu={_cpu_model()}"}
+
+
+def rel_l2(a, b) -> float:
+    import numpy as np
+
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def oracle_references(crop_out, grad_out):
+    """The other part of the CPU leg: the oracle's results that the GPU
+    legs' outputs are compared with.  Returns (accuracy of every storage
+    type on the 128^3 crop, accuracy and oracle time of the 48^3 gradient);
+    either is None when its GPU leg did not run."""
+    import numpy as np
+
+    import oracle
+    from paper_2204_03775_amd import inputs
+
+    threads = oracle.default_threads()
+    crop_acc = None
+    if crop_out:
+        p = inputs.crop_shot()
+        ref = oracle.run(p.k64(), p.h, p.nt, s=p.s, src=p.src, rec=p.rec, sponge_width=p.sponge_width,
+                         sponge_alpha=p.sponge_alpha, nthreads=threads)
+        crop_acc = {dt: {"rel_l2_field": rel_l2(f, ref[0]), "rel_l2_traces": rel_l2(tr, ref[2]),
+                         "workload": "128^3 crop of the large-shot model, own 20-cell sponge, 500 steps",
+                         "reference": "FP64 oracle"}
+                    for dt, (f, tr) in crop_out.items()}
+    grad_acc = None
+    if grad_out:
+        cg = inputs.gradient_crop()
+        c, co = cg.shot, cg.observed()
+        kw = dict(sponge_width=c.sponge_width, sponge_alpha=c.sponge_alpha, nthreads=threads)
+        t0 = time.perf_counter()
+        _, _, tr = oracle.run(c.k64(), c.h, c.nt, s=c.s, src=c.src, rec=c.rec, **kw)
+        t_fwd = time.perf_counter() - t0
+        _, _, tr_obs = oracle.run(co.k64(), co.h, co.nt, s=co.s, src=co.src, rec=co.rec, **kw)
+        r = tr - tr_obs
+        t0 = time.perf_counter()
+        ref = oracle.adjoint(c.k64(), c.h, c.nt, r, s=c.s, src=c.src, rec=c.rec, **kw)
+        t_orc = time.perf_counter() - t0 + t_fwd
+        J_ref = 0.5 * float(np.sum(r * r))
+        grad_acc = {"rel_l2_gradient_vs_oracle": rel_l2(grad_out["grad"], ref),
+                    "rel_misfit_vs_oracle": abs(grad_out["misfit"] - J_ref) / J_ref,
+                    "oracle_s": round(t_orc, 3), "oracle_threads": threads,
+                    "speedup_vs_oracle": round(t_orc / grad_out["gpu_s"], 1)}
+    return crop_acc, grad_acc
 
 
 def time_shots(prop, p, s, steps, warmup):
@@ -148,18 +207,15 @@ def result_ok(prop) -> bool:
                 and tr.abs().max().item() > 0)
 
 
-def crop_accuracy(threads):
-    """rel-L2 of the final field and traces against the FP64 oracle on the
-    128^3 crop (500 steps) for every storage type."""
+def crop_runs():
+    """Final field and traces of the 128^3 crop (500 steps) for every
+    storage type, on the GPU (compared with the oracle in the CPU leg)."""
     import numpy as np
     import torch
 
-    import oracle
     from paper_2204_03775_amd import inputs, wave
 
     p = inputs.crop_shot()
-    ref = oracle.run(p.k64(), p.h, p.nt, s=p.s, src=p.src, rec=p.rec, sponge_width=p.sponge_width,
-                     sponge_alpha=p.sponge_alpha, nthreads=threads)
     s = torch.tensor(p.s, dtype=torch.float32, device="cuda")
     out = {}
     for dt in ("f32", "f16", "bf16", "f16uv", "bf16uv"):
@@ -171,8 +227,7 @@ def crop_accuracy(threads):
         prop.sync()
         tr = prop.traces[:, :prop.nrec].cpu().numpy().astype(np.float64)
         prop.close()
-        out[dt] = {"rel_l2_field": float(np.linalg.norm(f - ref[0]) / np.linalg.norm(ref[0])),
-                   "rel_l2_traces": float(np.linalg.norm(tr - ref[2]) / np.linalg.norm(ref[2]))}
+        out[dt] = (f, tr)
     return out
 
 
@@ -243,11 +298,10 @@ def batched_leg(reps: int):
             "traces_bitwise_equal_to_sequential": bool(equal), "repeats": reps}
 
 
-def gradient_leg(reps: int, threads: int):
+def gradient_leg(reps: int):
     import numpy as np
     import torch
 
-    import oracle
     from paper_2204_03775_amd import inputs, wave
 
     gp = inputs.gradient_shot()
@@ -327,25 +381,10 @@ def gradient_leg(reps: int, threads: int):
     d2 = o2.traces[:, :o2.nrec].clone()
     t_gpu_crop, (Jc, gc) = timed(crop_gradient)
     gc = gc.cpu().numpy()
-    t0 = time.perf_counter()
-    _, _, tr = oracle.run(c.k64(), c.h, c.nt, s=c.s, src=c.src, rec=c.rec, sponge_width=c.sponge_width,
-                          sponge_alpha=c.sponge_alpha, nthreads=threads)
-    t_orc_fwd = time.perf_counter() - t0
-    _, _, tr_obs = oracle.run(co.k64(), co.h, co.nt, s=co.s, src=co.src, rec=co.rec,
-                              sponge_width=co.sponge_width, sponge_alpha=co.sponge_alpha,
-                              nthreads=threads)
-    r = tr - tr_obs
-    t0 = time.perf_counter()
-    ref = oracle.adjoint(c.k64(), c.h, c.nt, r, s=c.s, src=c.src, rec=c.rec,
-                         sponge_width=c.sponge_width, sponge_alpha=c.sponge_alpha, nthreads=threads)
-    t_orc = time.perf_counter() - t0 + t_orc_fwd
-    e_g = float(np.linalg.norm(gc - ref) / np.linalg.norm(ref))
-    J_ref = 0.5 * float(np.sum(r * r))
-    e_J = abs(Jc.item() - J_ref) / J_ref
     o2.close()
     cp.close()
-    log(f"gradient crop 48^3 x {c.nt}: rel-L2 vs oracle {e_g:.3e}, misfit rel {e_J:.2e}; GPU "
-        f"{t_gpu_crop * 1e3:.2f} ms, oracle {t_orc:.2f} s ({threads} threads)")
+    log(f"gradient crop 48^3 x {c.nt}: GPU {t_gpu_crop * 1e3:.2f} ms, misfit {Jc.item():.6e}")
+    crop_out = {"grad": gc, "misfit": Jc.item(), "gpu_s": t_gpu_crop}
     return {"workload": "256^3 x 800 steps FP32, 5 layers 1500-4500 m/s, +5% Gaussian anomaly "
                         "(sigma 8 cells, seed 2208), data from the model without it, 12 Hz "
                         "Ricker at (25,128,128), 128 receivers at z=22, 20-cell sponge",
@@ -363,11 +402,8 @@ def gradient_leg(reps: int, threads: int):
             "misfit": J50.item(),
             "crop": {"workload": "48^3 block around the anomaly, 8-cell sponge, 300 steps, "
                                  "28 receivers, checkpoints every 50",
-                     "rel_l2_gradient_vs_oracle": e_g, "rel_misfit_vs_oracle": e_J,
-                     "gpu_ms": round(t_gpu_crop * 1e3, 3), "oracle_s": round(t_orc, 3),
-                     "oracle_threads": threads,
-                     "speedup_vs_oracle": round(t_orc / t_gpu_crop, 1)},
-            "repeats": reps}
+                     "gpu_ms": round(t_gpu_crop * 1e3, 3)},
+            "repeats": reps}, crop_out
 
 
 def launch_leg(reps: int):
@@ -473,6 +509,7 @@ def main() -> int:
         f"{metrics.paper_tflops(gpts):.1f} TFLOP/s")
 
     forms = None
+    crop_out = grad_crop_out = None
     if not args.no_forms and args.workload == "large_shot":
         prop.close()
         forms = {}
@@ -498,15 +535,7 @@ def main() -> int:
                                       "bytes_per_point": bpp}}
             log(f"{dt}: {g16:.1f} Gpts/s ({g16 / gpts:.2f}x FP32), kernel {k16 * 1e6:.1f} us = "
                 f"{a16:.0f} GB/s at {bpp} B/pt")
-        acc = crop_accuracy(len(os.sched_getaffinity(0)))
-        for dt, a in acc.items():
-            a["workload"] = "128^3 crop of the large-shot model, own 20-cell sponge, 500 steps"
-            a["reference"] = "FP64 oracle"
-            if dt == "f32":
-                forms["f32_accuracy"] = a
-            else:
-                forms[dt]["accuracy"] = a
-            log(f"{dt} accuracy on the crop: field {a['rel_l2_field']:.3e} traces {a['rel_l2_traces']:.3e}")
+        crop_out = crop_runs()
 
     batched = None
     if not args.no_batched and args.workload == "large_shot":
@@ -523,16 +552,29 @@ def main() -> int:
     gradient = None
     if not args.no_gradient and args.workload == "large_shot":
         prop.close()
-        gradient = gradient_leg(max(2, args.steps), len(os.sched_getaffinity(0)))
+        gradient, grad_crop_out = gradient_leg(max(2, args.steps))
         if not (gradient["finite"] and gradient["bitwise_equal_across_checkpointing"]
                 and gradient["bitwise_equal_fused_two_passes"]):
             log("error: gradient not finite or dependent on the checkpoint interval")
             return 1
 
+    # the CPU leg: the oracle timed on the host cores, and its references
+    # for the accuracy reports of the other legs
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, args.cpu_seconds)
         log(f"oracle: {cpu['value']} Gpts/s ({cpu['sample']})")
+        crop_acc, grad_acc = oracle_references(crop_out, grad_crop_out)
+        for dt, a in (crop_acc or {}).items():
+            if dt == "f32":
+                forms["f32_accuracy"] = a
+            else:
+                forms[dt]["accuracy"] = a
+            log(f"{dt} accuracy on the crop: field {a['rel_l2_field']:.3e} traces {a['rel_l2_traces']:.3e}")
+        if grad_acc:
+            gradient["crop"].update(grad_acc)
+            log(f"gradient crop: rel-L2 vs oracle {grad_acc['rel_l2_gradient_vs_oracle']:.3e}, misfit rel "
+                f"{grad_acc['rel_misfit_vs_oracle']:.2e}; oracle {grad_acc['oracle_s']:.2f} s")
 
     rec = {
         "metric": "Gpts/s stencil updates + % HBM roofline (FP32 vs FP16-store); shots/s",
