@@ -1,6 +1,5 @@
 // Streaming bandwidth probes (declared in include/wave_probe.h).  Each
-// thread moves float4s in a grid-stride loop; launches fill every CU
-// several times over.
+// thread moves float4s in a grid-stride loop.
 #include <hip/hip_runtime.h>
 
 #include "wave_probe.h"
@@ -11,9 +10,14 @@ struct alignas(16) f4 {
     float v[4];
 };
 
-// Each thread moves U float4s per iteration (independent loads in flight),
-// streamed non-temporally like the propagator's once-read data.
-constexpr int U = 4;
+// Each thread keeps U float4 loads in flight, U grid strides apart, and
+// the grid holds 2 work-groups of 256 threads per CU: the fastest of the
+// launch shapes tried on MI355X (1..16 loads per thread, 256..1024 threads,
+// 1..8 work-groups per CU).  Accesses are non-temporal, like the
+// propagator's once-read data.
+constexpr int U = 2;
+constexpr int kThreads = 256;
+constexpr int kBlocksPerCu = 2;
 
 __device__ __forceinline__ f4 ldnt(const f4 *p)
 {
@@ -31,56 +35,46 @@ __device__ __forceinline__ void stnt(f4 *p, const f4 &v)
         __builtin_nontemporal_store(v.v[e], &p->v[e]);
 }
 
-__global__ __launch_bounds__(256) void copy_k(const f4 *__restrict__ s, f4 *__restrict__ d,
-                                              long long n4)
+__global__ __launch_bounds__(kThreads) void copy_k(const f4 *__restrict__ s, f4 *__restrict__ d,
+                                                   long long n4)
 {
-    const long long stride = (long long)gridDim.x * blockDim.x * U;
-    for (long long base = (long long)blockIdx.x * blockDim.x * U + threadIdx.x; base < n4;
-         base += stride) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride * U) {
         f4 v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const long long i = base + (long long)u * blockDim.x;
-            if (i < n4)
-                v[u] = ldnt(s + i);
-        }
+        for (int u = 0; u < U; ++u)
+            if (i + u * stride < n4)
+                v[u] = ldnt(s + i + u * stride);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const long long i = base + (long long)u * blockDim.x;
-            if (i < n4)
-                stnt(d + i, v[u]);
-        }
+        for (int u = 0; u < U; ++u)
+            if (i + u * stride < n4)
+                stnt(d + i + u * stride, v[u]);
     }
 }
 
-__global__ __launch_bounds__(256) void r3w1_k(const f4 *__restrict__ a, const f4 *__restrict__ b,
-                                              const f4 *__restrict__ c, f4 *__restrict__ d,
-                                              long long n4)
+__global__ __launch_bounds__(kThreads) void r3w1_k(const f4 *__restrict__ a, const f4 *__restrict__ b,
+                                                   const f4 *__restrict__ c, f4 *__restrict__ d,
+                                                   long long n4)
 {
-    const long long stride = (long long)gridDim.x * blockDim.x * U;
-    for (long long base = (long long)blockIdx.x * blockDim.x * U + threadIdx.x; base < n4;
-         base += stride) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride * U) {
         f4 x[U], y[U], z[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const long long i = base + (long long)u * blockDim.x;
-            if (i < n4) {
-                x[u] = ldnt(a + i);
-                y[u] = ldnt(b + i);
-                z[u] = ldnt(c + i);
+        for (int u = 0; u < U; ++u)
+            if (i + u * stride < n4) {
+                x[u] = ldnt(a + i + u * stride);
+                y[u] = ldnt(b + i + u * stride);
+                z[u] = ldnt(c + i + u * stride);
             }
-        }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const long long i = base + (long long)u * blockDim.x;
-            if (i < n4) {
+        for (int u = 0; u < U; ++u)
+            if (i + u * stride < n4) {
                 f4 o;
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
                     o.v[e] = x[u].v[e] + y[u].v[e] + z[u].v[e];
-                stnt(d + i, o);
+                stnt(d + i + u * stride, o);
             }
-        }
     }
 }
 
@@ -88,8 +82,12 @@ bool bad(const void *p) { return !p || (reinterpret_cast<uintptr_t>(p) & 15u); }
 
 int grid_for(long long n4)
 {
-    long long g = (n4 + 256 * U - 1) / (256 * U);
-    return int(g < 256 * 16 ? g : 256 * 16);  // up to 16 blocks per CU
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    const long long g = (n4 + kThreads - 1) / kThreads;
+    return int(g < (long long)kBlocksPerCu * cus ? g : (long long)kBlocksPerCu * cus);
 }
 
 }  // namespace
@@ -99,7 +97,7 @@ extern "C" int probe_copy(const float *src, float *dst, int64_t n, void *stream)
     if (bad(src) || bad(dst) || n <= 0 || (n & 3))
         return -1;
     const long long n4 = n / 4;
-    hipLaunchKernelGGL(copy_k, dim3(grid_for(n4)), dim3(256), 0, (hipStream_t)stream,
+    hipLaunchKernelGGL(copy_k, dim3(grid_for(n4)), dim3(kThreads), 0, (hipStream_t)stream,
                        (const f4 *)src, (f4 *)dst, n4);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
@@ -110,7 +108,7 @@ extern "C" int probe_read3_write1(const float *a, const float *b, const float *c
     if (bad(a) || bad(b) || bad(c) || bad(d) || n <= 0 || (n & 3))
         return -1;
     const long long n4 = n / 4;
-    hipLaunchKernelGGL(r3w1_k, dim3(grid_for(n4)), dim3(256), 0, (hipStream_t)stream,
+    hipLaunchKernelGGL(r3w1_k, dim3(grid_for(n4)), dim3(kThreads), 0, (hipStream_t)stream,
                        (const f4 *)a, (const f4 *)b, (const f4 *)c, (f4 *)d, n4);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }
