@@ -263,3 +263,66 @@ def test_autograd_directional_derivative(wave_mod, crop):
     an = float((gv * dt).sum().item())
     print(f"J {J.item():.6e}; directional derivative: adjoint {an:.6e}, central difference {fd:.6e}")
     assert abs(an - fd) <= 1e-2 * abs(fd)
+
+
+@pytest.mark.parametrize("shape,nt,every,sw", [((1, 1, 1), 3, 1, 0), ((5, 3, 2), 7, 3, 1),
+                                               ((13, 9, 40), 12, 5, 2), ((70, 3, 5), 9, 0, 1)])
+def test_adjoint_edge_shapes(wave_mod, oracle_lib, shape, nt, every, sw):
+    # tiny, flat and ragged grids; receivers repeated (their derivatives add)
+    import dataclasses
+
+    nx, ny, nz = shape
+    p = inputs.random_problem(nx, ny, nz, nt, seed=40 + nx, sponge_width=sw, sponge_alpha=0.2,
+                              nrec=5)
+    rec = np.concatenate([p.rec, p.rec[:2], p.rec[:1]]).astype(np.int32)
+    p = dataclasses.replace(p, rec=rec)
+    tg = np.random.default_rng(nx).standard_normal((nt, len(rec)))
+    print(f"case: adjoint {shape} x {nt}, every {every}, {len(rec)} receivers", flush=True)
+    got, _ = gpu_gradient(wave_mod, p, tg, every)
+    ref = oracle_lib.adjoint(p.k64(), p.h, nt, tg, s=p.s, src=p.src, rec=p.rec,
+                             sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+    e = rel(got, ref)
+    print(f"rel-L2 gradient {e:.3e}")
+    assert np.abs(ref).max() > 0 and e <= BOUND_ADJOINT
+
+
+def test_full_size_directional_derivative(wave_mod):
+    # the 256^3 x 800 gradient workload in the benchmark's configuration
+    # (checkpoints every 50 steps): <dJ/dk, dk> against a central difference
+    # of the GPU's own misfit along a smooth dk (the oracle's adjoint would
+    # need every level of the run, about 110 GB in FP64)
+    gp = inputs.gradient_shot()
+    p, q = gp.shot, gp.observed()
+    print(f"case: full-size gradient {p.shape} x {p.nt}", flush=True)
+    obs = make_prop(wave_mod, q)
+    obs.run(q.nt, src_of(q))
+    obs.sync()
+    d_obs = obs.traces[:, :obs.nrec].contiguous().clone()
+    obs.close()
+
+    def misfit_of(k32):
+        pr = wave_mod.Propagator(p.nx, p.ny, p.nz, p.h, k32, src=p.src, rec=p.rec,
+                                 sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+        pr.record(p.nt)
+        pr.forward_checkpointed(p.nt, src_of(p), gp.every)
+        J, res = wave_mod.misfit(pr.traces[:, :pr.nrec].contiguous(), d_obs)
+        return pr, J, res
+
+    k = p.k64()
+    pr, J, res = misfit_of(k.astype(np.float32))
+    g = pr.adjoint(res)
+    pr.sync()
+    g = g.cpu().numpy()
+    pr.close()
+    n = p.nx
+    c = gp.anomaly
+    z, y, x = np.ogrid[:n, :n, :n]
+    dk = 0.01 * k * np.exp(-((z - c[0]) ** 2 + (y - c[1]) ** 2 + (x - c[2]) ** 2) / (2 * 10.0 ** 2))
+    jp = [misfit_of((k + sgn * dk).astype(np.float32)) for sgn in (1, -1)]
+    fd = (jp[0][1].item() - jp[1][1].item()) / 2.0
+    for pr_, _, _ in jp:
+        pr_.close()
+    an = float(np.sum(g * dk))
+    print(f"J {J.item():.6e}; <dJ/dk, dk> {an:.6e}, central difference {fd:.6e}")
+    assert np.isfinite(g).all()
+    assert abs(an - fd) <= 1e-2 * abs(fd)

@@ -242,3 +242,29 @@ def test_step_points_matches_run(oracle_lib):
     got = oracle_lib.step_points(k32, c32, p32, p.h, pts, sponge_width=3,
                                  sponge_alpha=p.sponge_alpha, src=p.src, src_value=p.s[11])
     assert np.abs(got - nxt.ravel()).max() <= 1e-13 * np.abs(nxt).max()
+
+
+def test_stability_limit(oracle_lib):
+    # Leapfrog with a symmetric operator is stable iff K * lambda_max <= 4,
+    # lambda_max = (2048/315) sum_a 1/h_a^2 the largest eigenvalue of -lap
+    # (the Nyquist mode, present on an even periodic grid).  Just below the
+    # limit random data stay bounded; just above, the Nyquist mode grows
+    # like (1 + 2 sqrt(delta))^n.  This pins the limit the library checks
+    # at init and the workloads' dt rule.
+    from paper_2204_03775_amd.inputs import SYMBOL_MAX, stable_courant_limit
+
+    h = (9.0, 11.0, 7.0)
+    lam_max = SYMBOL_MAX * sum(1.0 / hh ** 2 for hh in h)
+    k_lim = 4.0 / lam_max
+    rng = np.random.default_rng(11)
+    u0 = rng.standard_normal((12, 14, 16))
+    peaks = {}
+    for f in (0.98, 1.01):
+        k = np.full(u0.shape, f * k_lim)
+        cur, _, _ = oracle_lib.run(k, h, 250, a_cur=u0, a_prev=u0, bc=oracle_lib.BC_PERIODIC)
+        peaks[f] = np.abs(cur).max() / np.abs(u0).max()
+    assert peaks[0.98] < 50.0, peaks
+    assert peaks[1.01] > 1e6, peaks
+    # the cubic-grid Courant limit used for dt: v dt / h <= 2 / sqrt(3 * 2048/315)
+    assert stable_courant_limit(3) == pytest.approx(2.0 / math.sqrt(3 * 2048 / 315), rel=1e-15)
+    assert stable_courant_limit(3) ** 2 * 3 * SYMBOL_MAX == pytest.approx(4.0, rel=1e-14)
