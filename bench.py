@@ -466,6 +466,7 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16 storage forms")
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-shot batched run")
     ap.add_argument("--no-gradient", action="store_true", help="skip the adjoint gradient leg")
+    ap.add_argument("--no-launch", action="store_true", help="skip the 64^3 graph-replay leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
 
@@ -546,7 +547,7 @@ def main() -> int:
             return 1
 
     launch = None
-    if args.workload == "large_shot":
+    if not args.no_launch and args.workload == "large_shot":
         launch = launch_leg(20)
 
     gradient = None

@@ -86,20 +86,20 @@ def traffic(a):
     ws = per_kernel(a.write_step, "WRITE_SIZE")
     fp = per_kernel(a.fetch_probe, "FETCH_SIZE")
     wp = per_kernel(a.write_probe, "WRITE_SIZE")
-    ks, kp = pick(fs, "step_tiled"), pick(fp, "copy_k")
+    ks, kp = pick(fs, a.match), pick(fp, "copy_k")
     avg = lambda v: sum(v) / len(v)
     copy_kib = a.probe_elements * 4 / 1024.0  # bytes read (= bytes written) by one copy
     f_scale = copy_kib / avg(fp[kp])
     w_scale = copy_kib / avg(wp[pick(wp, "copy_k")])
     fetch_b = avg(fs[ks]) * f_scale * 1024
-    write_b = avg(ws[pick(ws, "step_tiled")]) * w_scale * 1024
+    write_b = avg(ws[pick(ws, a.match)]) * w_scale * 1024
     algo_read, algo_write = 12 * a.points, 4 * a.points
     rec = {
         "kernel": a.kernel, "zchunk": a.zchunk,
         "source_sha256": source_digest(),
         "dispatches": len(fs[ks]),
         "fetch_kib_per_dispatch": round(avg(fs[ks]), 1),
-        "write_kib_per_dispatch": round(avg(ws[pick(ws, "step_tiled")]), 1),
+        "write_kib_per_dispatch": round(avg(ws[pick(ws, a.match)]), 1),
         "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
         "fetch_bytes_per_launch": round(fetch_b), "write_bytes_per_launch": round(write_b),
         "bytes_per_launch": round(fetch_b + write_b),
@@ -195,6 +195,8 @@ def main():
     for k in ("fetch-step", "write-step", "fetch-probe", "write-probe", "kernel", "out-json", "out-md"):
         t.add_argument("--" + k, required=True)
     t.add_argument("--zchunk", type=int, required=True)
+    t.add_argument("--match", default="step_tiled<0, 64, 8, 1>",
+                   help="kernel name substring (the FP32 step kernel of the variant)")
     t.add_argument("--points", type=int, required=True)
     t.add_argument("--probe-elements", type=int, required=True)
     t.add_argument("--commands", nargs="+", required=True)
