@@ -8,7 +8,8 @@ HBM before timing starts.  The JSON line on stdout carries:
 
   value      interior grid-point updates per second (Gpts/s) over the timed
              shots, wall clock between two device synchronisations;
-  roofline   the step kernel against the 8 TB/s HBM peak: 16 algorithmic
+  roofline   the step kernel against the 8 TB/s HBM peak (and against the
+             copy bandwidth measured in the same run): 16 algorithmic
              bytes per update (read u^n, u^{n-1}, k; write u^{n+1}) divided
              by its average launch time from HIP events on its stream;
              `traffic` is the HBM byte count per launch measured with
@@ -58,6 +59,9 @@ WORKLOADS = {
                   "at z=25, 256 receivers on a line (synthetic, seeded)",
     "small_parity": "64^3 x 100 steps FP32, v=1500 m/s, dt=1 ms, 15 Hz Ricker at the "
                     "centre, 16 random receivers, zero ghost layer (synthetic, seeded)",
+    "paper_shape": "755x994x1000 x 1000 steps FP32 (the paper's largest Table 2 shape), "
+                   "v=1500 m/s constant, dt=0.8 CFL, no sponge, 15 Hz Ricker at the centre, "
+                   "256 receivers (synthetic; context for the paper's cell rates)",
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_large_shot.json")
 # the sources of the FP32 step kernel (types, device code, instantiation)
@@ -505,6 +509,13 @@ def main() -> int:
     launch_bytes = metrics.BYTES_PER_POINT_F32 * p.points
     achieved = launch_bytes / kernel_s / 1e9
     traffic = measured_traffic(kname, zchunk) if args.workload == "large_shot" else None
+    copy_gbs = None
+    try:
+        from paper_2204_03775_amd import probe
+
+        copy_gbs = probe.measure(wave.wave_layout(512, 512, 512).elems, repeats=10)["copy_gbs"]
+    except ImportError:
+        pass
     log(f"{gpts:.1f} Gpts/s wall, kernel {kernel_s * 1e6:.1f} us/launch = {achieved:.0f} GB/s "
         f"({achieved / metrics.MI355X_HBM_PEAK_GBS:.3f} of peak), paper-convention "
         f"{metrics.paper_tflops(gpts):.1f} TFLOP/s")
@@ -599,7 +610,9 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                      "peak": metrics.MI355X_HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / metrics.MI355X_HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     "copy_gbs_measured": copy_gbs,
+                     "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None},
         "cpu_baseline": cpu,
         "forms": forms,
         "batched": batched,

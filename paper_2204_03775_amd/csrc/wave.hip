@@ -192,7 +192,10 @@ void sponge_profile(int n, int width, double alpha, std::vector<float> &g)
 //     rows to keep enough bytes in flight: 128 x 32 tiles of two rows per
 //     thread at 256 work-groups run 594 Gpts/s against 482 for 256 x 8;
 //   - u-and-change storage (five streams) does best with 128 x 16 tiles of
-//     two rows per thread at 512 work-groups (478 against 361).
+//     two rows per thread at 512 work-groups (478 against 361);
+//   - in every case the best z split fills whole rounds of the work-groups
+//     the GPU holds at once (one or two per CU here): 755 x 994 tiles of
+//     256 x 8 in one chunk are 375 work-groups, a round and a half of 256.
 // Every chunk re-reads 8 planes of u^n, so chunks are kept at >= 32 planes.
 // Grids of fewer than 2^22 cells fit in the caches and are latency-bound:
 // there, about 512 work-groups with chunks down to one plane run 3-6x
@@ -202,11 +205,24 @@ constexpr int kAutoVariant = 10;     // t256x8_r1 (FP32)
 constexpr int kAuto16Variant = 12;   // t128x32_r2 (FP16 / BF16, two levels)
 constexpr int kAutoUvVariant = 4;    // t128x16_r2 (u-and-change storage)
 constexpr int kSmallVariant = 2;     // t64x16_r1 for grids of fewer than 2^22 cells
-constexpr int kTargetWorkgroups = 256;
-constexpr int kTargetWorkgroupsUv = 512;
 constexpr int kTargetWorkgroupsSmall = 512;
 constexpr int kMinChunk = 32;
 constexpr int kMinChunkSmall = 1;
+
+// Work-groups of the tiled kernel of variant v that the current GPU holds at
+// once (occupancy per CU times CUs).
+long long resident_workgroups(int kind, int v)
+{
+    const Variant &V = kVariants[v];
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    const StepKernel f = kind == WAVE_F32 || V.fn[kind] ? V.fn[kind] : V.fn[WAVE_F32];
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, V.txv * V.ty, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return (long long)per_cu * cus;
+}
 
 Geo plan_geo(int nx, int ny, int nz, int kind, int variant, int zchunk)
 {
@@ -215,8 +231,6 @@ Geo plan_geo(int nx, int ny, int nz, int kind, int variant, int zchunk)
     const bool large = (long long)nx * ny * nz >= (1ll << 22);
     if (v == 0)
         v = !large ? kSmallVariant : kind == WAVE_F32 ? kAutoVariant : is_uv(kind) ? kAutoUvVariant : kAuto16Variant;
-    const long long target = !large ? kTargetWorkgroupsSmall : is_uv(kind) ? kTargetWorkgroupsUv : kTargetWorkgroups;
-    const int min_chunk = large ? kMinChunk : kMinChunkSmall;
     g.v = v;
     if (v == kNaive) {
         g.ntx = g.nty = g.nchunks = 0;
@@ -231,10 +245,29 @@ Geo plan_geo(int nx, int ny, int nz, int kind, int variant, int zchunk)
     g.nty = (ny + tyr - 1) / tyr;
     const long long tiles = (long long)g.ntx * g.nty;
     int zc = zchunk;
-    if (zc <= 0) {
-        const long long chunks = std::max(1ll, (target + tiles / 2) / tiles);
-        zc = int((nz + chunks - 1) / chunks);
-        zc = std::max(zc, std::min(min_chunk, nz));
+    if (zc <= 0 && !large) {
+        const long long chunks = std::max(1ll, (kTargetWorkgroupsSmall + tiles / 2) / tiles);
+        zc = std::max(int((nz + chunks - 1) / chunks), std::min(kMinChunkSmall, nz));
+    } else if (zc <= 0) {
+        // fill whole rounds of the work-groups the GPU holds at once: the
+        // chunk count maximising work-groups / (rounds x capacity), each
+        // chunk charged for re-reading 8 planes of u^n (a quarter of the
+        // bytes per update: factor 1 + 2 / zc); chunks stay >= 32 planes
+        const long long cap = resident_workgroups(kind, v);
+        double best = -1.0;
+        zc = nz;
+        for (int c = 1; c <= nz; ++c) {
+            const int z = (nz + c - 1) / c;
+            if (z < std::min(kMinChunk, nz))
+                break;
+            const long long nwg = tiles * ((nz + z - 1) / z);
+            const long long rounds = (nwg + cap - 1) / cap;
+            const double eff = double(nwg) / double(rounds * cap) / (1.0 + 2.0 / z);
+            if (eff > best + 1e-12) {
+                best = eff;
+                zc = z;
+            }
+        }
     }
     if (zc > nz)
         zc = nz;

@@ -31,6 +31,9 @@ The paper runs on synthetic grids whose velocity model it does not state
   Ricker at
   (25, 128, 128), 128 receivers at z = 22, y = 128, x = 20..235;
   checkpoints every 50 steps (gradient of the least-squares misfit).
+* ``paper_shape``: the paper's largest Table 2 shape, 755 x 994 x 1000
+  (x, y, z), 1000 steps, constant 1500 m/s (its model is not stated), no
+  sponge: a context run for the paper's cell-rate figures.
 * ``gradient_crop``: the 48^3 block of both models centred on the anomaly,
   8-cell sponge (alpha 0.04), 300 steps, source at (12, 24, 24),
   28 receivers at z = 10, y = 24, x = 10..37 (checks of the gradient).
@@ -306,3 +309,20 @@ def gradient_crop(nt: int = 300, m: int = 48) -> GradientProblem:
     shot = Problem("gradient_crop", m, m, m, h, dt, nt, 8, 0.04, src, rec,
                    point_source_values(w, float(ve[src]), dt, h), ve)
     return GradientProblem(shot, vb, 50, tuple(m // 2 for _ in range(3)))
+
+
+def paper_shape(nt: int = 1000) -> Problem:
+    """The paper's largest Table 2 shape, 755 x 994 x 1000 (x, y, z) with
+    1000 steps, in a constant 1500 m/s medium (the paper does not state its
+    model): h = 10 m, dt = 0.8 of the stability limit, zero ghost layer, no
+    sponge, 15 Hz Ricker at the centre, 256 receivers on a line.  Context
+    run for a like-for-like cell rate against the paper's figures."""
+    nx, ny, nz = 755, 994, 1000
+    h = (10.0, 10.0, 10.0)
+    dt = cfl_dt(1500.0, 10.0, 0.8)
+    v = np.full((nz, ny, nx), 1500.0, dtype=np.float32)
+    src = (nz // 2, ny // 2, nx // 2)
+    rec = line_receivers(nz // 2 - 20, ny // 2, 20, nx - 21, 256)
+    w = ricker(15.0, nt, dt)
+    return Problem("paper_shape", nx, ny, nz, h, dt, nt, 0, 0.0, src, rec,
+                   point_source_values(w, 1500.0, dt, h), v)
