@@ -447,6 +447,18 @@ def launch_leg(reps: int):
             "graph_gpts_per_s": round(p.points * p.nt / t_graph / 1e9, 3), "repeats": reps}
 
 
+def _git_sha():
+    """HEAD of the source tree when it is a git checkout, else None."""
+    import subprocess
+
+    try:
+        r = subprocess.run(["git", "-C", ROOT, "rev-parse", "HEAD"], capture_output=True, text=True,
+                           timeout=10)
+        return r.stdout.strip() or None
+    except (OSError, subprocess.SubprocessError):
+        return None
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -606,7 +618,9 @@ def main() -> int:
                    "kernel": kname, "zchunk": zchunk, "workgroups": nwg,
                    "shots_per_s": round(args.steps / wall, 4),
                    "paper_tflops_51flop": round(metrics.paper_tflops(gpts), 2),
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "step_kernel_source_sha256": source_digest(),
+                   "git": _git_sha()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                      "peak": metrics.MI355X_HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / metrics.MI355X_HBM_PEAK_GBS, 4),

@@ -179,6 +179,12 @@ const char *wave_variant_name(int32_t variant);
 /* Variant and z-chunk in use, and the work-groups one step launches. */
 int wave_config(const wave_ctx *ctx, int32_t *variant, int32_t *zchunk, int32_t *workgroups);
 
+/* Watchdog: counts the non-finite values (infinity, NaN) of the current
+ * field u^n (interior) and of the trace rows written so far.  Either count
+ * pointer may be NULL.  Synchronises the context's stream; a run that went
+ * unstable (for instance a k edited after init) shows up here. */
+int wave_check(wave_ctx *ctx, int64_t *field_nonfinite, int64_t *trace_nonfinite);
+
 /* Wait for all work enqueued on the context's stream; WAVE_EHIP if it or
  * any earlier launch failed. */
 int wave_sync(wave_ctx *ctx);

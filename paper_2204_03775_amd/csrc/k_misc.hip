@@ -114,4 +114,35 @@ __global__ __launch_bounds__(256) void k_range(const float *__restrict__ k, int 
     }
 }
 
+// Counts non-finite values: the interior of a field (FP32 or 16-bit bits,
+// by storage type) into out[0], n trace values into out[1].
+__global__ __launch_bounds__(256) void count_nonfinite(const void *__restrict__ field, int kind, int nx,
+                                                      int ny, int nz, int px, int x0, long long plane,
+                                                      const float *__restrict__ traces, long long n,
+                                                      int *out)
+{
+    const long long cells = (long long)nx * ny * nz;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    int bad_f = 0, bad_t = 0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cells; i += stride) {
+        const int x = (int)(i % nx);
+        const int y = (int)((i / nx) % ny);
+        const int z = (int)(i / ((long long)nx * ny));
+        const long long p = (long long)(z + kGhost) * plane + (long long)(y + kGhost) * px + x0 + x;
+        if (kind == WAVE_F32) {
+            bad_f += !isfinite(static_cast<const float *>(field)[p]);
+        } else {
+            const unsigned b = static_cast<const unsigned short *>(field)[p];
+            const unsigned e = (kind == WAVE_F16 || kind == WAVE_F16_UV) ? 0x7c00u : 0x7f80u;
+            bad_f += (b & e) == e;  // all-ones exponent: infinity or NaN
+        }
+    }
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        bad_t += !isfinite(traces[i]);
+    if (bad_f)
+        atomicAdd(&out[0], bad_f);
+    if (bad_t)
+        atomicAdd(&out[1], bad_t);
+}
+
 }  // namespace wavek

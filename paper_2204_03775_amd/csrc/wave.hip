@@ -1278,6 +1278,36 @@ int wave_adjoint(wave_ctx *ctx, const float *trace_grad_dev, double *grad_dev, i
     return WAVE_OK;
 }
 
+int wave_check(wave_ctx *ctx, int64_t *field_nonfinite, int64_t *trace_nonfinite)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    int *d = nullptr;
+    int h[2] = {0, 0};
+    HIP_TRY(ctx, hipMalloc(&d, 2 * sizeof(int)));
+    const long long cells = (long long)ctx->p.nx * ctx->p.ny * ctx->p.nz;
+    const long long nt = (ctx->traces && ctx->nrec > 0) ? std::min<long long>(ctx->step, ctx->trace_cap) : 0;
+    bool ok = hipMemsetAsync(d, 0, 2 * sizeof(int), ctx->stream) == hipSuccess;
+    if (ok) {
+        const dim3 g((unsigned)std::min<long long>((std::max(cells, nt * ctx->nrec) + 255) / 256, 4096));
+        hipLaunchKernelGGL(count_nonfinite, g, dim3(256), 0, ctx->stream, (const void *)ctx->cur,
+                           ctx->p.dtype, ctx->p.nx, ctx->p.ny, ctx->p.nz, int(ctx->lay.pitch_x),
+                           int(ctx->lay.x_offset), (long long)ctx->lay.plane, (const float *)ctx->traces,
+                           nt * ctx->nrec, d);
+        ok = hipGetLastError() == hipSuccess &&
+             hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, ctx->stream) == hipSuccess &&
+             hipStreamSynchronize(ctx->stream) == hipSuccess;
+    }
+    (void)hipFree(d);
+    if (!ok)
+        return fail(ctx, WAVE_EHIP, "wave_check failed");
+    if (field_nonfinite)
+        *field_nonfinite = h[0];
+    if (trace_nonfinite)
+        *trace_nonfinite = h[1];
+    return WAVE_OK;
+}
+
 int wave_set_adjoint_fusion(wave_ctx *ctx, int32_t on)
 {
     if (!ctx)

@@ -141,6 +141,10 @@ __global__ void inject_receivers(float *phi, const float *__restrict__ k,
 __global__ __launch_bounds__(1024) void misfit_kernel(const float *__restrict__ tr,
                                                       const float *__restrict__ obs, long long n,
                                                       float *residual, double *out);
+__global__ __launch_bounds__(256) void count_nonfinite(const void *__restrict__ field, int kind, int nx,
+                                                      int ny, int nz, int px, int x0, long long plane,
+                                                      const float *__restrict__ traces, long long n,
+                                                      int *out);
 __global__ __launch_bounds__(256) void grad_to_dense(const double *__restrict__ acc, double *dense, int nx,
                                                     int ny, int nz, int px, int x0, long long plane,
                                                     int accumulate);

@@ -84,6 +84,7 @@ def _load():
         "wave_adjoint": ([vp, vp, vp, i32], ci),
         "wave_set_adjoint_fusion": ([vp, i32], ci),
         "wave_set_graph": ([vp, i32], ci),
+        "wave_check": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], ci),
         "wave_grad_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                             ctypes.POINTER(i64)], ci),
         "wave_misfit": ([vp, vp, i64, vp, vp, vp], ci),
@@ -217,6 +218,12 @@ def wave_adjoint(ctx, trace_grad_ptr, grad_ptr, accumulate: bool = False):
     _check(_lib.wave_adjoint(ctx, trace_grad_ptr, grad_ptr, int(bool(accumulate))), ctx)
 
 
+def wave_check(ctx):
+    f, t = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.wave_check(ctx, ctypes.byref(f), ctypes.byref(t)), ctx)
+    return f.value, t.value
+
+
 def wave_set_graph(ctx, on: bool):
     _check(_lib.wave_set_graph(ctx, int(bool(on))), ctx)
 
@@ -294,10 +301,12 @@ class Propagator:
     torch) of V^2 dt^2, rounded to FP32 once.  ``dtype`` selects the field
     storage: "f32"; "f16" / "bf16" (two 16-bit time levels, FP32
     arithmetic); "f16uv" / "bf16uv" (16-bit u^n and step change d^n, the
-    latter held by the library)."""
+    latter held by the library).  ``u_cur`` / ``u_prev`` (dense, FP32
+    storage only) give the state to start from, e.g. to resume a run."""
 
     def __init__(self, nx, ny, nz, h, k, *, src=None, rec=None, sponge_width=0,
-                 sponge_alpha=0.0, stream=None, device=None, dtype="f32"):
+                 sponge_alpha=0.0, stream=None, device=None, dtype="f32", u_cur=None,
+                 u_prev=None):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.h = tuple(float(v) for v in h)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -312,6 +321,13 @@ class Propagator:
         self.buf = [torch.zeros(n, dtype=tdt, device=self.device),
                     torch.zeros(n, dtype=tdt, device=self.device)]
         self.interior(self.k).copy_(torch.as_tensor(k).to(device=self.device, dtype=torch.float32))
+        if u_cur is not None or u_prev is not None:
+            # a state to resume from (the library starts 16-bit fields from zero)
+            if self.dtype != WAVE_F32:
+                raise ValueError("initial fields are supported for FP32 storage only")
+            for b, u in zip(self.buf, (u_cur, u_prev)):
+                if u is not None:
+                    self.interior(b).copy_(torch.as_tensor(u).to(device=self.device, dtype=torch.float32))
         self.src = tuple(int(v) for v in src) if src is not None else None
         self.rec = rec
         self.nrec = 0 if rec is None else len(rec)
@@ -410,6 +426,10 @@ class Propagator:
         """(steps, segment length, segments, checkpoint bytes) of the last
         checkpointed run."""
         return wave_grad_info(self.ctx)
+
+    def check(self):
+        """(non-finite values in u^n, non-finite trace values so far)."""
+        return wave_check(self.ctx)
 
     def use_graph(self, on: bool = True):
         """Replay repeated runs from a captured HIP graph (needs a

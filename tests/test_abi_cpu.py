@@ -126,3 +126,7 @@ def test_misfit_rejects_bad_arguments(w):
     assert lib.wave_misfit(dummy, dummy, -1, None, dummy, None) == w.WAVE_EINVAL
     assert lib.wave_misfit(dummy, dummy, 4, None, None, None) == w.WAVE_EINVAL
     assert lib.wave_misfit(None, dummy, 4, None, dummy, None) == w.WAVE_EINVAL
+
+
+def test_check_rejects_null_context(w):
+    assert w.lib().wave_check(None, None, None) == w.WAVE_EINVAL
