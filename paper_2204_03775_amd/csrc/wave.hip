@@ -16,6 +16,7 @@
 
 #include "wave.h"
 #include "wave_dev.h"
+#include "wave_kernels.h"
 
 using namespace wavek;
 
