@@ -27,7 +27,9 @@ HBM before timing starts.  The JSON line on stdout carries:
              storage type against the FP64 oracle on a 128^3 crop of the
              same model (500 steps);
   batched    32 uneven shots (96..320 x 96..320 x 96..256, 600 steps each,
-             FP32) as one autotuned batch replayed from a HIP graph: shots/s
+             FP32) as one autotuned batch replayed from a HIP graph (the
+             tuner picks the schedule: one persistent launch per step, or
+             every shot with its own tuned kernel on a few streams): shots/s
              and aggregate Gpts/s, against the same 32 shots run one after
              another with the library's automatic configuration (their
              traces must agree bit for bit).
@@ -269,6 +271,7 @@ def batched_leg(reps: int):
     choice = autotune.tune_batch(props, srcs, stream, log=log)
     t_tune = time.perf_counter() - t
     b = wave.Batch(props, stream=stream, use_graph=True)
+    b.set_schedule(choice["schedule"], choice["nstreams"])
     groups, wgs, _ = b.info()
 
     def once():
@@ -290,15 +293,19 @@ def batched_leg(reps: int):
     for pr in props:
         pr.close()
     gpts = points * nt / t_batch / 1e9
-    log(f"batched: 32 shots in {t_batch * 1e3:.1f} ms ({32 / t_batch:.1f} shots/s, {gpts:.1f} Gpts/s, "
-        f"{groups} launch groups, {wgs} work-groups/step); sequential {t_seq * 1e3:.1f} ms; "
-        f"speedup {t_seq / t_batch:.2f}x; traces equal: {equal}; tuning {t_tune:.1f} s")
+    sched = ("one persistent launch per step and kernel group" if choice["schedule"] == 0 else
+             f"every shot with its own tuned kernel on {choice['nstreams']} streams")
+    log(f"batched ({sched}): 32 shots in {t_batch * 1e3:.1f} ms ({32 / t_batch:.1f} shots/s, "
+        f"{gpts:.1f} Gpts/s); sequential {t_seq * 1e3:.1f} ms; speedup {t_seq / t_batch:.2f}x; "
+        f"traces equal: {equal}; tuning {t_tune:.1f} s")
     return {"workload": "32 shots (seed 2207), 96..320 x 96..320 x 96..256, 3..6 layers, "
                         "10..20 Hz Ricker, 20-cell sponge, 128 receivers, 600 steps, FP32",
             "shots_per_s": round(32 / t_batch, 3), "value": round(gpts, 3), "unit": "Gpts/s",
             "batched_ms": round(t_batch * 1e3, 2), "sequential_ms": round(t_seq * 1e3, 2),
             "speedup_vs_sequential": round(t_seq / t_batch, 3), "graph": True,
-            "launch_groups": groups, "tuned": {k: list(v) for k, v in choice.items()},
+            "schedule": choice["schedule"], "schedule_name": sched, "nstreams": choice["nstreams"],
+            "tuning_us_per_step": {k: round(v, 1) for k, v in choice["us_per_step"].items()},
+            "launch_groups": groups if choice["schedule"] == 0 else None,
             "traces_bitwise_equal_to_sequential": bool(equal), "repeats": reps}
 
 

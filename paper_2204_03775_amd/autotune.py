@@ -1,12 +1,18 @@
-"""Tile and z-chunk selection per size class, measured on the GPU.
+"""Tile, z-chunk and schedule selection, measured on the GPU.
 
-Shots are grouped into size classes by the x extent of their grid (the
-axis tiles are widest along, so it decides how many lanes of the last tile
-idle).  For a batch, every class gets a kernel variant and a z-chunk
-fraction; candidates are timed on the batch itself, one class at a time
-(coordinate descent from a common start), because a configuration that is
-best for a shot running alone (many z-chunks to fill the GPU) is not best
-when 32 shots share the GPU (chunks re-read 8 planes each).
+Single shots: every (variant, z-chunk) candidate is timed on the shot's
+own grid (``tune_single``).
+
+Batches (``tune_batch``) can run in two ways.  Schedule 0 puts all shots
+into one persistent launch per step and kernel group; there shots are
+grouped into size classes by the x extent of their grid (the axis tiles
+are widest along, so it decides how many lanes of the last tile idle), and
+every class gets a kernel variant and a z-chunk fraction, timed on the
+batch itself one class at a time (coordinate descent from a common
+start), because a configuration that is best for a shot alone is not best
+when all shots share each launch.  Schedule 1 launches every shot with its
+own tuned configuration, spread over a few streams and replayed from one
+graph.  The faster of the two is kept.
 
 Results are cached in a JSON file keyed by (GPU architecture, storage type,
 class); ``WAVE_TUNE_CACHE`` overrides its location.
@@ -73,14 +79,17 @@ def apply(props, choice: dict) -> None:
         p.configure(name, zc)
 
 
-def time_batch(props, srcs, nsteps: int, stream) -> float:
-    """Seconds per step of one batched run (eager launches, after a short
-    warm-up); fields are reset before and after."""
-    b = wave.Batch(props, stream=stream, use_graph=False)
+def time_batch(props, srcs, nsteps: int, stream, schedule: int = 0, nstreams: int = 1) -> float:
+    """Seconds per step of one batched run, after a short warm-up; fields
+    are reset before and after.  Schedule 0 launches eagerly (one launch per
+    step and group); schedule 1 is captured once and the replay is timed."""
+    b = wave.Batch(props, stream=stream, use_graph=(schedule == 1))
     try:
+        if schedule:
+            b.set_schedule(schedule, nstreams)
         for p in props:
             p.reset()
-        b.run(3, srcs)
+        b.run(3 if not schedule else nsteps, srcs)
         b.sync()
         for p in props:
             p.reset()
@@ -97,8 +106,80 @@ def time_batch(props, srcs, nsteps: int, stream) -> float:
             p.reset()
 
 
+SINGLE_CHUNKS = (0, 8, 16, 32, 64)  # z-chunk (0: the library's automatic choice)
+STREAM_COUNTS = (1, 2, 4)
+
+
+def _single_key(p) -> str:
+    return f"{arch()}|{p.dtype}|shot|{p.nx}x{p.ny}x{p.nz}"
+
+
+def tune_single(prop, src, stream, nsteps: int = 20, use_cache: bool = True, log=None):
+    """The fastest (variant, z-chunk) for one Propagator alone, measured on
+    its own grid (cached per GPU architecture, storage type and shape);
+    leaves it configured with that choice and returns it."""
+    cache = load_cache() if use_cache else {}
+    key = _single_key(prop)
+    if key in cache:
+        name, zc = cache[key]
+        prop.configure(name, zc)
+        return name, zc
+    best = None
+    for name in VARIANTS:
+        for zc in SINGLE_CHUNKS:
+            if zc > prop.nz:
+                continue
+            prop.configure(name, zc)
+            prop.reset()
+            prop.run(3, src)
+            ps = prop.stream  # the Propagator's own stream
+            with torch.cuda.stream(ps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(ps)
+                prop.run(nsteps, src[3:] if src is not None else None)
+                e1.record(ps)
+            ps.synchronize()
+            t = e0.elapsed_time(e1) / nsteps
+            if best is None or t < best[0]:
+                best = (t, name, zc)
+    prop.reset()
+    _, name, zc = best
+    if log:
+        log(f"tune {prop.nx}x{prop.ny}x{prop.nz}: {name} zc {zc}: {best[0] * 1e3:.1f} us/step")
+    prop.configure(name, zc)
+    if use_cache:
+        cache = load_cache()
+        cache[key] = [name, zc]
+        save_cache(cache)
+    return name, zc
+
+
 def tune_batch(props, srcs, stream, nsteps: int = 30, use_cache: bool = True, log=None) -> dict:
-    """Choose (variant, chunks) per size class for this batch; returns
+    """Choose how to run this batch: schedule 0 (one persistent launch per
+    step and group) with a (variant, chunks) per size class, or schedule 1
+    (every shot with its own tuned configuration on 1, 2 or 4 streams),
+    whichever is faster.  Configures the Propagators and returns
+    {"schedule", "nstreams", "classes" or "shots", "us_per_step"}; create
+    the Batch afterwards and call its set_schedule(schedule, nstreams)."""
+    classes = tune_classes(props, srcs, stream, nsteps, use_cache, log)
+    t_queue = time_batch(props, srcs, nsteps, stream)
+    shots = [tune_single(p, s, stream, use_cache=use_cache, log=log) for p, s in zip(props, srcs)]
+    t_streams = {k: time_batch(props, srcs, nsteps, stream, schedule=1, nstreams=k) for k in STREAM_COUNTS}
+    k_best = min(t_streams, key=t_streams.get)
+    if log:
+        log(f"tune batch: schedule 0 {t_queue * 1e6:.1f} us/step; schedule 1 "
+            + ", ".join(f"{k} streams {t * 1e6:.1f}" for k, t in t_streams.items()) + " us/step")
+    times = {"schedule0": t_queue * 1e6, **{f"schedule1_streams{k}": t * 1e6 for k, t in t_streams.items()}}
+    if t_streams[k_best] < t_queue:
+        return {"schedule": 1, "nstreams": k_best, "shots": [list(x) for x in shots],
+                "us_per_step": times}
+    apply(props, classes)
+    return {"schedule": 0, "nstreams": 1, "classes": {k: list(v) for k, v in classes.items()},
+            "us_per_step": times}
+
+
+def tune_classes(props, srcs, stream, nsteps: int = 30, use_cache: bool = True, log=None) -> dict:
+    """Choose (variant, chunks) per size class for schedule 0; returns
     {class: (variant, chunks)} and configures the Propagators with it."""
     classes = sorted({size_class(p.nx) for p in props},
                      key=lambda c: -sum(p.points for p in props if size_class(p.nx) == c))

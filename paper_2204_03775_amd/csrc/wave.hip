@@ -203,12 +203,15 @@ void sponge_profile(int n, int width, double alpha, std::vector<float> &g)
 // faster per step than 32-plane chunks (48^3: 3.9 against 24.8 us per
 // step; 128^3: 9.5 against 25.9; 192^3: about 25 against 29).
 constexpr int kAutoVariant = 10;     // t256x8_r1 (FP32)
+constexpr int kAutoNarrowVariant = 3;  // t128x8_r1 (FP32 when 256-wide tiles would idle lanes)
 constexpr int kAuto16Variant = 12;   // t128x32_r2 (FP16 / BF16, two levels)
 constexpr int kAutoUvVariant = 4;    // t128x16_r2 (u-and-change storage)
 constexpr int kSmallVariant = 2;     // t64x16_r1 for grids of fewer than 2^22 cells
 constexpr int kTargetWorkgroupsSmall = 512;
 constexpr int kMinChunk = 32;
 constexpr int kMinChunkSmall = 1;
+constexpr int kMinChunkNarrow = 8;
+constexpr int kMaxChunkNarrow = 16;
 
 // Work-groups of the tiled kernel of variant v that the current GPU holds at
 // once (occupancy per CU times CUs).
@@ -230,8 +233,15 @@ Geo plan_geo(int nx, int ny, int nz, int kind, int variant, int zchunk)
     Geo g;
     int v = variant;
     const bool large = (long long)nx * ny * nz >= (1ll << 22);
+    // FP32 grids whose x extent leaves more than 5 % of a 256-wide tile's
+    // lanes idle take 128 x 8 tiles (three work-groups per CU) and more,
+    // shorter chunks
+    const bool narrow = large && kind == WAVE_F32 && variant == 0 &&
+                        double(nx) / (256.0 * ((nx + 255) / 256)) < 0.95;
     if (v == 0)
-        v = !large ? kSmallVariant : kind == WAVE_F32 ? kAutoVariant : is_uv(kind) ? kAutoUvVariant : kAuto16Variant;
+        v = !large ? kSmallVariant
+                   : kind == WAVE_F32 ? (narrow ? kAutoNarrowVariant : kAutoVariant)
+                                      : is_uv(kind) ? kAutoUvVariant : kAuto16Variant;
     g.v = v;
     if (v == kNaive) {
         g.ntx = g.nty = g.nchunks = 0;
@@ -249,6 +259,14 @@ Geo plan_geo(int nx, int ny, int nz, int kind, int variant, int zchunk)
     if (zc <= 0 && !large) {
         const long long chunks = std::max(1ll, (kTargetWorkgroupsSmall + tiles / 2) / tiles);
         zc = std::max(int((nz + chunks - 1) / chunks), std::min(kMinChunkSmall, nz));
+    } else if (zc <= 0 && narrow) {
+        // about 1.2 rounds of resident work-groups, chunks of 8..16 planes
+        // (measured on 112 x 304 x 240 .. 448 x 320 x 320: 1.1-1.4x the
+        // 256 x 8 plan, within about 10 % of the best of 27 choices)
+        const long long target = (resident_workgroups(kind, v) * 6) / 5;
+        const long long chunks = std::max(1ll, (target + tiles / 2) / tiles);
+        zc = std::min(std::max(int((nz + chunks - 1) / chunks), kMinChunkNarrow), kMaxChunkNarrow);
+        zc = std::min(zc, nz);
     } else if (zc <= 0) {
         // fill whole rounds of the work-groups the GPU holds at once: the
         // chunk count maximising work-groups / (rounds x capacity), each
@@ -679,6 +697,12 @@ struct wave_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_steps = -1;
+    // schedule 1: every shot launched with its own configuration, shots
+    // dealt round-robin to these streams (fork and join through events)
+    int schedule = 0;
+    std::vector<hipStream_t> aux;
+    std::vector<hipEvent_t> ev;  // fork, then one join per stream
+    std::vector<int64_t> key;    // the run the graph was captured for
     long long points = 0, workgroups = 0;
     std::string err;
 };
@@ -698,7 +722,7 @@ int bfail(wave_batch *b, int code, const char *fmt, ...)
     return code;
 }
 
-void batch_free(wave_batch *b)
+void drop_batch_graph(wave_batch *b)
 {
     if (b->exec)
         (void)hipGraphExecDestroy(b->exec);
@@ -706,10 +730,57 @@ void batch_free(wave_batch *b)
         (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
+    b->graph_steps = -1;
+    b->key.clear();
+}
+
+void drop_streams(wave_batch *b)
+{
+    for (hipStream_t s : b->aux)
+        (void)hipStreamDestroy(s);
+    for (hipEvent_t e : b->ev)
+        (void)hipEventDestroy(e);
+    b->aux.clear();
+    b->ev.clear();
+}
+
+void batch_free(wave_batch *b)
+{
+    drop_batch_graph(b);
+    drop_streams(b);
     for (auto &g : b->groups) {
         free_dev(g.d_desc);
         free_dev(g.d_items);
     }
+}
+
+// Schedule 1: each shot's steps on stream i % K with the shot's own kernel;
+// the contexts' bookkeeping advances as the launches are enqueued.
+int batch_enqueue_streams(wave_batch *b, int nsteps, const float *const *src_dev)
+{
+    const size_t K = b->aux.size();
+    if (hipEventRecord(b->ev[0], b->stream) != hipSuccess)
+        return WAVE_EHIP;
+    for (size_t k = 0; k < K; ++k)
+        if (hipStreamWaitEvent(b->aux[k], b->ev[0], 0) != hipSuccess)
+            return WAVE_EHIP;
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+        wave_ctx *c = b->ctx[i];
+        hipStream_t saved = c->stream;
+        c->stream = b->aux[i % K];
+        const float *src = src_dev ? src_dev[i] : nullptr;
+        int rc = WAVE_OK;
+        for (int j = 0; j < nsteps && rc == WAVE_OK; ++j)
+            rc = launch_step(c, src ? src + j : nullptr, 0.f);
+        c->stream = saved;
+        if (rc != WAVE_OK)
+            return rc;
+    }
+    for (size_t k = 0; k < K; ++k)
+        if (hipEventRecord(b->ev[1 + k], b->aux[k]) != hipSuccess ||
+            hipStreamWaitEvent(b->stream, b->ev[1 + k], 0) != hipSuccess)
+            return WAVE_EHIP;
+    return WAVE_OK;
 }
 
 int batch_enqueue(wave_batch *b, int nsteps)
@@ -1494,6 +1565,65 @@ int wave_batch_run(wave_batch *b, int32_t nsteps, const float *const *src_dev)
     }
     if (n0 + nsteps > 0x3fffffff)
         return bfail(b, WAVE_EINVAL, "step counter out of range");
+    if (b->schedule == 1) {
+        if (nsteps == 0)
+            return WAVE_OK;
+        std::vector<int64_t> key = {nsteps};
+        for (size_t i = 0; i < b->ctx.size(); ++i) {
+            const wave_ctx *c = b->ctx[i];
+            key.insert(key.end(), {c->step, (int64_t)(uintptr_t)c->cur, (int64_t)(uintptr_t)c->prev,
+                                   (int64_t)(uintptr_t)c->traces,
+                                   (int64_t)(uintptr_t)(src_dev ? src_dev[i] : nullptr)});
+        }
+        if (b->use_graph && b->exec && key == b->key) {
+            if (hipGraphLaunch(b->exec, b->stream) != hipSuccess)
+                return bfail(b, WAVE_EHIP, "graph launch failed");
+            for (wave_ctx *c : b->ctx) {  // the captured launches' bookkeeping
+                c->step += nsteps;
+                if (nsteps & 1)
+                    std::swap(c->cur, c->prev);
+            }
+            return WAVE_OK;
+        }
+        std::vector<std::pair<void *, void *>> roles;
+        for (wave_ctx *c : b->ctx)
+            roles.push_back({c->cur, c->prev});
+        auto restore = [&]() {
+            for (size_t i = 0; i < b->ctx.size(); ++i) {
+                b->ctx[i]->step = n0;
+                b->ctx[i]->cur = roles[i].first;
+                b->ctx[i]->prev = roles[i].second;
+            }
+        };
+        if (!b->use_graph) {
+            if (batch_enqueue_streams(b, nsteps, src_dev) != WAVE_OK)
+                return bfail(b, WAVE_EHIP, "batched launch failed");
+            return WAVE_OK;
+        }
+        drop_batch_graph(b);
+        if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return bfail(b, WAVE_EHIP, "graph capture could not start");
+        const int rc = batch_enqueue_streams(b, nsteps, src_dev);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->stream, &g);
+        if (rc != WAVE_OK || e != hipSuccess || !g) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            restore();
+            return bfail(b, WAVE_EHIP, "graph capture failed");
+        }
+        if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            b->exec = nullptr;
+            restore();
+            return bfail(b, WAVE_EHIP, "graph instantiation failed");
+        }
+        b->graph = g;
+        b->key = key;
+        if (hipGraphLaunch(b->exec, b->stream) != hipSuccess)
+            return bfail(b, WAVE_EHIP, "graph launch failed");
+        return WAVE_OK;
+    }
     // descriptors of this run; upload only what changed (after the work
     // that may still read the old ones)
     bool synced = false;
@@ -1560,6 +1690,36 @@ int wave_batch_run(wave_batch *b, int32_t nsteps, const float *const *src_dev)
             void *t = c->prev;
             c->prev = c->cur;
             c->cur = t;
+        }
+    }
+    return WAVE_OK;
+}
+
+int wave_batch_set_schedule(wave_batch *b, int32_t schedule, int32_t nstreams)
+{
+    if (!b)
+        return WAVE_EINVAL;
+    if (schedule < 0 || schedule > 1 || (schedule == 1 && (nstreams < 1 || nstreams > 16)))
+        return bfail(b, WAVE_EINVAL, "schedule must be 0, or 1 with 1..16 streams");
+    if (schedule == 1 && b->use_graph && !b->stream)
+        return bfail(b, WAVE_EINVAL, "graph replay needs a stream other than the legacy default stream");
+    if (hipStreamSynchronize(b->stream) != hipSuccess)
+        return bfail(b, WAVE_EHIP, "stream synchronisation failed");
+    drop_batch_graph(b);
+    drop_streams(b);
+    b->schedule = schedule;
+    if (schedule == 1) {
+        for (int k = 0; k < nstreams; ++k) {
+            hipStream_t st = nullptr;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+                return bfail(b, WAVE_EHIP, "stream creation failed");
+            b->aux.push_back(st);
+        }
+        for (int k = 0; k <= nstreams; ++k) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+                return bfail(b, WAVE_EHIP, "event creation failed");
+            b->ev.push_back(e);
         }
     }
     return WAVE_OK;

@@ -90,6 +90,7 @@ def _load():
         "wave_misfit": ([vp, vp, i64, vp, vp, vp], ci),
         "wave_batch_create": ([ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp, i32], ci),
         "wave_batch_run": ([vp, i32, ctypes.POINTER(vp)], ci),
+        "wave_batch_set_schedule": ([vp, i32, i32], ci),
         "wave_batch_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64)], ci),
         "wave_batch_sync": ([vp], ci),
         "wave_batch_destroy": ([vp], ci),
@@ -273,6 +274,10 @@ def wave_batch_run(b, nsteps: int, src_ptrs=None):
     if src_ptrs is not None:
         arr = (ctypes.c_void_p * len(src_ptrs))(*[p or None for p in src_ptrs])
     _bcheck(_lib.wave_batch_run(b, nsteps, arr), b)
+
+
+def wave_batch_set_schedule(b, schedule: int, nstreams: int = 1):
+    _bcheck(_lib.wave_batch_set_schedule(b, int(schedule), int(nstreams)), b)
 
 
 def wave_batch_info(b):
@@ -476,6 +481,12 @@ class Batch:
         self.props = list(props)
         self.stream = stream if stream is not None else torch.cuda.Stream(self.props[0].device)
         self.handle = wave_batch_create([p.ctx for p in self.props], self.stream.cuda_stream, use_graph)
+
+    def set_schedule(self, schedule: int, nstreams: int = 1):
+        """0: one persistent launch per step and kernel group; 1: every
+        shot with its own kernel on ``nstreams`` streams."""
+        wave_batch_set_schedule(self.handle, schedule, nstreams)
+        self.schedule, self.nstreams = int(schedule), int(nstreams)
 
     def info(self):
         """(launch groups, work-groups per step, interior points per step)"""

@@ -1,5 +1,6 @@
-"""Batched multi-shot runs (one launch per step for many shots, optionally
-replayed from a HIP graph).
+"""Batched multi-shot runs: one persistent launch per step for many shots
+(schedule 0) or every shot with its own kernel over several streams
+(schedule 1), optionally replayed from a HIP graph.
 
 Exact: every shot of a batch reproduces, bit for bit, the same shot run
 alone with the same kernel configuration -- fields, buffer roles and
@@ -161,13 +162,56 @@ def test_autotune_choice_is_applied(wave_mod, tmp_path, monkeypatch):
     shots = make_shots()
     props, srcs = build(wave_mod, shots, "f32")
     stream = torch.cuda.Stream()
-    choice = autotune.tune_batch(props, srcs, stream, nsteps=5)
-    assert set(choice) == {autotune.size_class(p.nx) for p in shots}
+    # per-class choice (schedule 0), served from the cache the second time
+    classes = autotune.tune_classes(props, srcs, stream, nsteps=5)
+    assert set(classes) == {autotune.size_class(p.nx) for p in shots}
     for p, pr in zip(shots, props):
-        name, parts = choice[autotune.size_class(p.nx)]
+        name, parts = classes[autotune.size_class(p.nx)]
         v, zc, _ = pr.config()
         assert wave_mod.wave_variant_name(v) == name and zc == -(-p.nz // parts)
-    # second call is served from the cache
-    assert autotune.tune_batch(props, srcs, stream) == choice
+    assert autotune.tune_classes(props, srcs, stream) == classes
+    # per-shot choice, cached per shape
+    one = autotune.tune_single(props[0], srcs[0], stream, nsteps=5)
+    assert autotune.tune_single(props[0], srcs[0], stream) == one
+    # the whole batch: a schedule, and the shots configured for it
+    choice = autotune.tune_batch(props, srcs, stream, nsteps=5)
+    assert choice["schedule"] in (0, 1) and choice["nstreams"] >= 1
+    if choice["schedule"] == 1:
+        for pr, (name, zc) in zip(props, choice["shots"]):
+            v, zc_used, _ = pr.config()
+            assert wave_mod.wave_variant_name(v) == name and (zc == 0 or zc_used == zc)
+    b = wave_mod.Batch(props, stream=stream)
+    b.set_schedule(choice["schedule"], choice["nstreams"])
+    b.run(shots[0].nt, srcs)
+    b.sync()
+    b.close()
+    for pr in props:
+        pr.close()
+
+
+@pytest.mark.parametrize("nstreams,graph", [(1, False), (3, False), (3, True)])
+def test_per_shot_schedule_matches_individual_runs(wave_mod, nstreams, graph):
+    shots = make_shots()
+    ref = alone(wave_mod, shots, "f32")
+    props, srcs = build(wave_mod, shots, "f32")
+    b = wave_mod.Batch(props, use_graph=graph)
+    b.set_schedule(1, nstreams)
+    nt = shots[0].nt
+    junk = torch.randn(1 << 20, device="cuda")
+    for rep in range(3 if graph else 1):
+        print(f"case: schedule 1, {nstreams} streams, graph={graph}, replay {rep}", flush=True)
+        for pr in props:
+            pr.reset()
+        if graph:  # the same run each time: captured once, then replayed
+            b.run(nt, srcs)
+        else:  # split in an odd and an even part (role bookkeeping)
+            b.run(9, srcs)
+            b.run(nt - 9, [s[9:] for s in srcs])
+        junk.mul_(1.0001)
+        b.sync()
+        torch.cuda.synchronize()
+        for i, pr in enumerate(props):
+            assert same(snapshot(pr), ref[i]), (rep, i)
+    b.close()
     for pr in props:
         pr.close()
