@@ -454,6 +454,83 @@ def launch_leg(reps: int):
             "graph_gpts_per_s": round(p.points * p.nt / t_graph / 1e9, 3), "repeats": reps}
 
 
+# The paper's measurements for its scaling shapes, for context beside the
+# MI355X rates.  Table 2: 1000 steps; throughput in Gcell/s on the WSE-2,
+# and elapsed seconds on the WSE-2 and on an A100.  Table 3: 755 x 994 x nz,
+# 100,000 steps; throughput in Gcell/s and elapsed seconds on the WSE-2.
+PAPER_TABLE2 = {(200, 200, 1000): (533.64, 0.0750, 0.7892),
+                (400, 400, 1000): (2097.60, 0.0763, 3.5828),
+                (600, 600, 1000): (4731.53, 0.0761, 8.0000),
+                (755, 500, 1000): (4956.17, 0.0762, 8.5499),
+                (755, 600, 1000): (5945.40, 0.0762, 10.1362),
+                (755, 900, 1000): (8922.08, 0.0762, 15.5070),
+                (755, 990, 1000): (9782.14, 0.0764, 17.4991),
+                (755, 994, 1000): (9862.78, 0.0761, 17.4186)}
+PAPER_TABLE3 = {(755, 994, 100): (8688.76, 0.8637), (755, 994, 200): (9303.26, 1.6133),
+                (755, 994, 300): (9492.89, 2.3716), (755, 994, 400): (9614.15, 3.1223),
+                (755, 994, 500): (9786.51, 3.8342), (755, 994, 700): (9885.04, 5.3143),
+                (755, 994, 1000): (9936.79, 7.5524)}
+
+
+def paper_shapes_leg(nt: int):
+    """Every grid shape of the paper's two scaling tables, FP32 with the
+    library's automatic plan, nt steps after a short warm-up: Gcell/s on
+    this GPU beside the paper's WSE-2 rate and the A100 rate its Table 2
+    times imply (cells x 1000 steps / seconds)."""
+    import numpy as np
+    import torch
+
+    from paper_2204_03775_amd import inputs, wave
+
+    rows = []
+    for table, shapes in (("Table 2", inputs.PAPER_TABLE2_SHAPES),
+                          ("Table 3", inputs.PAPER_TABLE3_SHAPES)):
+        for nx, ny, nz in shapes:
+            p = inputs.paper_shape(nt, nx, ny, nz)
+            kval = float(np.float32((np.float64(1500.0) * p.dt) ** 2))
+            stream = torch.cuda.Stream()
+            k = torch.full((1, 1, 1), kval, dtype=torch.float32, device="cuda").expand(nz, ny, nx)
+            prop = wave.Propagator(nx, ny, nz, p.h, k, src=p.src, rec=p.rec, stream=stream)
+            del k
+            prop.record(nt)
+            s = torch.tensor(p.s, dtype=torch.float32, device="cuda")
+            with torch.cuda.stream(stream):
+                prop.reset()
+            prop.run(20, s)
+            with torch.cuda.stream(stream):
+                prop.reset()
+            stream.synchronize()
+            t0 = time.perf_counter()
+            prop.run(nt, s)
+            stream.synchronize()
+            sec = time.perf_counter() - t0
+            ok = result_ok(prop)
+            variant, zchunk, nwg = prop.config()
+            kname = wave.wave_variant_name(variant)
+            prop.close()
+            del prop, s
+            torch.cuda.empty_cache()
+            gcell = p.points * nt / sec / 1e9
+            row = {"table": table, "nx": nx, "ny": ny, "nz": nz, "mi355x_gcell_per_s": round(gcell, 1),
+                   "kernel": kname, "zchunk": zchunk, "workgroups": nwg, "finite": ok}
+            if table == "Table 2":
+                wse, t_wse, t_a100 = PAPER_TABLE2[(nx, ny, nz)]
+                row.update(wse2_gcell_per_s=wse,
+                           a100_gcell_per_s=round(p.points * 1000 / t_a100 / 1e9, 1),
+                           vs_a100=round(gcell * t_a100 / (p.points * 1000 / 1e9), 2))
+            else:
+                wse, t_wse = PAPER_TABLE3[(nx, ny, nz)]
+                row.update(wse2_gcell_per_s=wse)
+            row["vs_wse2"] = round(gcell / wse, 4)
+            log(f"paper shape {table} {nx}x{ny}x{nz}: {gcell:.1f} Gcell/s ({kname}, z-chunk {zchunk}, "
+                f"{nwg} work-groups); WSE-2 {wse} Gcell/s" +
+                (f", A100 {row['a100_gcell_per_s']}" if table == "Table 2" else ""))
+            rows.append(row)
+    return {"workload": f"the paper's Table 2 and Table 3 grid shapes, {nt} steps each, FP32, "
+                        "v=1500 m/s constant, no sponge, automatic launch plan",
+            "steps": nt, "rows": rows}
+
+
 def _git_sha():
     """HEAD of the source tree when it is a git checkout, else None."""
     import subprocess
@@ -490,6 +567,8 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-shot batched run")
     ap.add_argument("--no-gradient", action="store_true", help="skip the adjoint gradient leg")
     ap.add_argument("--no-launch", action="store_true", help="skip the 64^3 graph-replay leg")
+    ap.add_argument("--no-paper-shapes", action="store_true",
+                    help="skip the sweep over the paper's Table 2 and Table 3 grid shapes")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
 
@@ -580,6 +659,14 @@ def main() -> int:
     if not args.no_launch and args.workload == "large_shot":
         launch = launch_leg(20)
 
+    paper_shapes = None
+    if not args.no_paper_shapes and args.workload == "large_shot":
+        prop.close()
+        paper_shapes = paper_shapes_leg(300)
+        if not all(r["finite"] for r in paper_shapes["rows"]):
+            log("error: a paper-shape run produced non-finite or empty output")
+            return 1
+
     gradient = None
     if not args.no_gradient and args.workload == "large_shot":
         prop.close()
@@ -639,6 +726,7 @@ def main() -> int:
         "batched": batched,
         "gradient": gradient,
         "launch": launch,
+        "paper_shapes": paper_shapes,
     }
     prop.close()
     print(json.dumps(rec), flush=True)

@@ -764,10 +764,24 @@ int batch_enqueue_streams(wave_batch *b, int nsteps, const float *const *src_dev
     for (size_t k = 0; k < K; ++k)
         if (hipStreamWaitEvent(b->aux[k], b->ev[0], 0) != hipSuccess)
             return WAVE_EHIP;
-    for (size_t i = 0; i < b->ctx.size(); ++i) {
+    // Largest shots first, each to the stream with the least work so far
+    // (work = cells per step), so the streams end close together.
+    std::vector<size_t> order(b->ctx.size());
+    for (size_t i = 0; i < order.size(); ++i)
+        order[i] = i;
+    auto cells = [&](size_t i) {
+        const wave_params_t &p = b->ctx[i]->p;
+        return (double)p.nx * p.ny * p.nz;
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t x, size_t y) { return cells(x) > cells(y); });
+    std::vector<double> load(K, 0.0);
+    for (const size_t i : order) {
+        const size_t k = std::min_element(load.begin(), load.end()) - load.begin();
+        load[k] += cells(i);
         wave_ctx *c = b->ctx[i];
         hipStream_t saved = c->stream;
-        c->stream = b->aux[i % K];
+        c->stream = b->aux[k];
         const float *src = src_dev ? src_dev[i] : nullptr;
         int rc = WAVE_OK;
         for (int j = 0; j < nsteps && rc == WAVE_OK; ++j)

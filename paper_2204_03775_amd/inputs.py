@@ -311,18 +311,28 @@ def gradient_crop(nt: int = 300, m: int = 48) -> GradientProblem:
     return GradientProblem(shot, vb, 50, tuple(m // 2 for _ in range(3)))
 
 
-def paper_shape(nt: int = 1000) -> Problem:
-    """The paper's largest Table 2 shape, 755 x 994 x 1000 (x, y, z) with
-    1000 steps, in a constant 1500 m/s medium (the paper does not state its
-    model): h = 10 m, dt = 0.8 of the stability limit, zero ghost layer, no
-    sponge, 15 Hz Ricker at the centre, 256 receivers on a line.  Context
-    run for a like-for-like cell rate against the paper's figures."""
-    nx, ny, nz = 755, 994, 1000
+# Grid shapes of the paper's scaling experiments (x, y, z): Table 2 grows
+# x and y at nz = 1000, Table 3 grows nz at 755 x 994.
+PAPER_TABLE2_SHAPES = ((200, 200, 1000), (400, 400, 1000), (600, 600, 1000),
+                       (755, 500, 1000), (755, 600, 1000), (755, 900, 1000),
+                       (755, 990, 1000), (755, 994, 1000))
+PAPER_TABLE3_SHAPES = tuple((755, 994, nz) for nz in (100, 200, 300, 400, 500, 700, 1000))
+
+
+def paper_shape(nt: int = 1000, nx: int = 755, ny: int = 994, nz: int = 1000) -> Problem:
+    """A grid shape of the paper's scaling experiments (default: the largest
+    Table 2 shape, 755 x 994 x 1000) with nt steps, in a constant 1500 m/s
+    medium (the paper does not state its model): h = 10 m, dt = 0.8 of the
+    stability limit, zero ghost layer, no sponge, 15 Hz Ricker at the centre,
+    up to 256 receivers on a line.  Context runs for a like-for-like cell
+    rate against the paper's figures.  ``v`` is a read-only broadcast view
+    (no dense copy)."""
     h = (10.0, 10.0, 10.0)
     dt = cfl_dt(1500.0, 10.0, 0.8)
-    v = np.full((nz, ny, nx), 1500.0, dtype=np.float32)
+    v = np.broadcast_to(np.float32(1500.0), (nz, ny, nx))
     src = (nz // 2, ny // 2, nx // 2)
-    rec = line_receivers(nz // 2 - 20, ny // 2, 20, nx - 21, 256)
+    x0, x1 = 20, nx - 21
+    rec = line_receivers(max(0, nz // 2 - 20), ny // 2, x0, x1, min(256, x1 - x0 + 1))
     w = ricker(15.0, nt, dt)
     return Problem("paper_shape", nx, ny, nz, h, dt, nt, 0, 0.0, src, rec,
                    point_source_values(w, 1500.0, dt, h), v)
