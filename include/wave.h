@@ -32,8 +32,10 @@
  *   extends each column by 4 cells on both sides; here the same is done on
  *   all three axes).  Interior point (z, y, x), 0 <= x < nx etc., is element
  *       ((z + 4) * (ny + 8) + (y + 4)) * pitch_x + x_offset + x.
- *   Ghost cells must be zero in u fields (zero Dirichlet boundary) and the
- *   library never writes them.  x_offset makes every interior row start on a
+ *   Ghost cells must be zero in u fields (zero Dirichlet boundary) and stay
+ *   so: the library writes nothing but zero into them (when nx is not a
+ *   multiple of 4, a row's last 4-cell group, which ends in right-ghost
+ *   cells, is stored whole).  x_offset makes every interior row start on a
  *   128-byte boundary.
  */
 #ifndef WAVE_H

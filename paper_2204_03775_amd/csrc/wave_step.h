@@ -168,16 +168,6 @@ __device__ __forceinline__ void store4(__amdgpu_buffer_rsrc_t r, unsigned off, c
     }
 }
 
-template <int KIND>
-__device__ __forceinline__ void store1(__amdgpu_buffer_rsrc_t r, unsigned off, float v, float inv)
-{
-    if constexpr (KIND == WAVE_F32)
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, kStream);
-    else
-        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)Store<KIND>::enc(v * inv), r, off, 0,
-                                              kStream);
-}
-
 // Element read outside the hot loop (receivers, exports).
 template <int KIND>
 __device__ __forceinline__ float read_elem(const void *f, long long i, float scale)
@@ -731,26 +721,26 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
                     for (int e = 0; e < 4; ++e)
                         dn.v[e] = 0.5f * (out.v[e] - fd.a * ctr.v[e]);
                 }
-                if (col_full) {
-                    store4<KIND>(ro, own_in[r], out, 1.f);
-                    if constexpr (UV)
-                        store4<KIND>(rdl, own_in[r], dn, 1.f);
-                    if constexpr (SCALED) {
-                        if (row_int[r]) {
+                // In a ragged last group the cells past nx are right-ghost
+                // cells, which hold zero: writing zero there keeps them so and
+                // lets the group go out as one whole store (no partial writes).
+                if (!col_full) {
 #pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                tmax = fmaxf(tmax, fabsf(out.v[e]));
+                    for (int e = 0; e < 4; ++e)
+                        if (x + e >= a.nx) {
+                            out.v[e] = 0.f;
+                            if constexpr (UV)
+                                dn.v[e] = 0.f;
                         }
-                    }
-                } else if (row_int[r]) {
+                }
+                store4<KIND>(ro, own_in[r], out, 1.f);
+                if constexpr (UV)
+                    store4<KIND>(rdl, own_in[r], dn, 1.f);
+                if constexpr (SCALED) {
+                    if (row_int[r]) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const bool in = x + e < a.nx;
-                        store1<KIND>(ro, in ? own_in[r] + EB * e : kOff, out.v[e], 1.f);
-                        if constexpr (UV)
-                            store1<KIND>(rdl, in ? own_in[r] + EB * e : kOff, dn.v[e], 1.f);
-                        if constexpr (SCALED)
-                            tmax = in ? fmaxf(tmax, fabsf(out.v[e])) : tmax;
+                        for (int e = 0; e < 4; ++e)
+                            tmax = fmaxf(tmax, fabsf(out.v[e]));
                     }
                 }
             }

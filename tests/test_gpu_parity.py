@@ -174,7 +174,7 @@ def test_buffer_roles_after_odd_and_even_counts(wave_mod, nt):
     prop.close()
 
 
-def test_ghost_cells_never_written(wave_mod):
+def test_ghost_cells_stay_zero(wave_mod):
     p = inputs.random_problem(29, 13, 11, 30, seed=5, sponge_width=2)
     prop = wave_mod.Propagator(p.nx, p.ny, p.nz, p.h, p.k32(), src=p.src)
     prop.run(p.nt, torch.tensor(p.s, dtype=torch.float32, device="cuda"))
