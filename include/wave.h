@@ -283,15 +283,19 @@ int wave_batch_run(wave_batch *b, int32_t nsteps, const float *const *src_dev);
  *   schedule 0  one persistent launch per step for every group of shots
  *               sharing a kernel (work items taken by ticket), the default;
  *   schedule 1  every shot's steps launched with its own kernel
- *               configuration, the shots dealt round-robin to nstreams
- *               (1..16) streams of the library that fork from and join back
- *               to the batch stream; with use_graph the whole run is one
+ *               configuration, the shots dealt, largest first, to the least
+ *               loaded (in cells) of nstreams (1..16) streams of the library
+ *               that fork from and join back to the batch stream; with
+ *               use_graph the whole run is one
  *               captured graph, replayed while the shots' states, sources,
  *               trace buffers and nsteps repeat.  Shots large enough to
  *               fill the GPU alone run best this way, each with the tiling
  *               that suits its own shape.
  * Both give the same results bit for bit as the shots run alone.  Waits for
- * the batch stream; drops a captured graph. */
+ * the batch stream; drops a captured graph.  WAVE_EINVAL for another
+ * schedule, a stream count out of range, or schedule 1 with graph replay on
+ * the legacy default stream; WAVE_EHIP if the library's streams or events
+ * cannot be created, and the batch is then left on schedule 0. */
 int wave_batch_set_schedule(wave_batch *b, int32_t schedule, int32_t nstreams);
 
 /* Launch groups, work-groups and interior points of one batched step. */

@@ -203,7 +203,7 @@ void sponge_profile(int n, int width, double alpha, std::vector<float> &g)
 // faster per step than 32-plane chunks (48^3: 3.9 against 24.8 us per
 // step; 128^3: 9.5 against 25.9; 192^3: about 25 against 29).
 constexpr int kAutoVariant = 10;     // t256x8_r1 (FP32)
-constexpr int kAutoNarrowVariant = 3;  // t128x8_r1 (FP32 when 256-wide tiles would idle lanes)
+constexpr int kAutoNarrowVariant = 6;  // t128x16_r1 (FP32 when 256-wide tiles would idle lanes)
 constexpr int kAuto16Variant = 12;   // t128x32_r2 (FP16 / BF16, two levels)
 constexpr int kAutoUvVariant = 4;    // t128x16_r2 (u-and-change storage)
 constexpr int kSmallVariant = 2;     // t64x16_r1 for grids of fewer than 2^22 cells
@@ -211,11 +211,14 @@ constexpr int kTargetWorkgroupsSmall = 512;
 constexpr int kMinChunk = 32;
 constexpr int kMinChunkSmall = 1;
 constexpr int kMinChunkNarrow = 8;
-constexpr int kMaxChunkNarrow = 16;
 
 // Work-groups of the tiled kernel of variant v that the current GPU holds at
 // once (occupancy per CU times CUs).
-long long resident_workgroups(int kind, int v)
+// Work-groups of variant v that make one round: 8 waves (512 threads) per
+// CU, as one work-group of 512 threads or two of 256, bounded by how many
+// fit at once (occupancy API).  Two resident 512-thread work-groups per CU
+// measured slower than one: they split the CU's bandwidth and add a tail.
+long long round_workgroups(int kind, int v)
 {
     const Variant &V = kVariants[v];
     int dev = 0, cus = 0, per_cu = 0;
@@ -223,9 +226,43 @@ long long resident_workgroups(int kind, int v)
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
         cus = 256;
     const StepKernel f = kind == WAVE_F32 || V.fn[kind] ? V.fn[kind] : V.fn[WAVE_F32];
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, V.txv * V.ty, 0) != hipSuccess || per_cu < 1)
+    const int threads = V.txv * V.ty;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, threads, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    return (long long)per_cu * cus;
+    return (long long)cus * std::min(per_cu, std::max(1, 512 / threads));
+}
+
+// z-chunk length for a grid of `tiles` x-y tiles and rounds of `cap`
+// work-groups: the chunk count that maximises
+//     nwg / (R cap) * 0.85^(R-1) / (1 + 2/zc),   R = ceil(nwg / cap).
+// The step time follows the rounds the busiest CU runs, so work-group counts
+// just under a multiple of a round are the efficient ones; each further
+// round costs about 15 % beyond its share (idle time at the hand-over), and
+// each chunk re-reads 8 planes of u^n (a quarter of the bytes per update:
+// factor 1 + 2/zc).  Chunks stay >= min_chunk planes (or nz).  Fitted on
+// 16 grids from 112 x 304 x 240 to 600 x 1200 x 200, every chunk count
+// measured, with 128 x 16 tiles; the other large-grid plans it gives are
+// the ones measured best before it.
+int fill_rounds_chunk(long long tiles, int nz, int min_chunk, long long cap)
+{
+    double best = -1.0;
+    int zc = nz;
+    for (int c = 1; c <= nz; ++c) {
+        const int z = (nz + c - 1) / c;
+        if (z < std::min(min_chunk, nz))
+            break;
+        if (c > 1 && z == (nz + c - 2) / (c - 1))
+            continue;  // the same chunk length as c - 1
+        const long long nwg = tiles * ((nz + z - 1) / z);
+        const long long rounds = (nwg + cap - 1) / cap;
+        const double eff = double(nwg) / double(rounds * cap) * std::pow(0.85, double(rounds - 1)) /
+                           (1.0 + 2.0 / z);
+        if (eff > best + 1e-12) {
+            best = eff;
+            zc = z;
+        }
+    }
+    return zc;
 }
 
 Geo plan_geo(int nx, int ny, int nz, int kind, int variant, int zchunk)
@@ -234,8 +271,7 @@ Geo plan_geo(int nx, int ny, int nz, int kind, int variant, int zchunk)
     int v = variant;
     const bool large = (long long)nx * ny * nz >= (1ll << 22);
     // FP32 grids whose x extent leaves more than 5 % of a 256-wide tile's
-    // lanes idle take 128 x 8 tiles (three work-groups per CU) and more,
-    // shorter chunks
+    // lanes idle take 128 x 16 tiles
     const bool narrow = large && kind == WAVE_F32 && variant == 0 &&
                         double(nx) / (256.0 * ((nx + 255) / 256)) < 0.95;
     if (v == 0)
@@ -259,34 +295,10 @@ Geo plan_geo(int nx, int ny, int nz, int kind, int variant, int zchunk)
     if (zc <= 0 && !large) {
         const long long chunks = std::max(1ll, (kTargetWorkgroupsSmall + tiles / 2) / tiles);
         zc = std::max(int((nz + chunks - 1) / chunks), std::min(kMinChunkSmall, nz));
-    } else if (zc <= 0 && narrow) {
-        // about 1.2 rounds of resident work-groups, chunks of 8..16 planes
-        // (measured on 112 x 304 x 240 .. 448 x 320 x 320: 1.1-1.4x the
-        // 256 x 8 plan, within about 10 % of the best of 27 choices)
-        const long long target = (resident_workgroups(kind, v) * 6) / 5;
-        const long long chunks = std::max(1ll, (target + tiles / 2) / tiles);
-        zc = std::min(std::max(int((nz + chunks - 1) / chunks), kMinChunkNarrow), kMaxChunkNarrow);
-        zc = std::min(zc, nz);
     } else if (zc <= 0) {
-        // fill whole rounds of the work-groups the GPU holds at once: the
-        // chunk count maximising work-groups / (rounds x capacity), each
-        // chunk charged for re-reading 8 planes of u^n (a quarter of the
-        // bytes per update: factor 1 + 2 / zc); chunks stay >= 32 planes
-        const long long cap = resident_workgroups(kind, v);
-        double best = -1.0;
-        zc = nz;
-        for (int c = 1; c <= nz; ++c) {
-            const int z = (nz + c - 1) / c;
-            if (z < std::min(kMinChunk, nz))
-                break;
-            const long long nwg = tiles * ((nz + z - 1) / z);
-            const long long rounds = (nwg + cap - 1) / cap;
-            const double eff = double(nwg) / double(rounds * cap) / (1.0 + 2.0 / z);
-            if (eff > best + 1e-12) {
-                best = eff;
-                zc = z;
-            }
-        }
+        // large grids: whole rounds, chunks of at least 32 planes (8 for
+        // the narrow-grid tiles, whose tiles are few)
+        zc = fill_rounds_chunk(tiles, nz, narrow ? kMinChunkNarrow : kMinChunk, round_workgroups(kind, v));
     }
     if (zc > nz)
         zc = nz;
@@ -754,7 +766,7 @@ void batch_free(wave_batch *b)
     }
 }
 
-// Schedule 1: each shot's steps on stream i % K with the shot's own kernel;
+// Schedule 1: each shot's steps on one of the K streams with the shot's own kernel;
 // the contexts' bookkeeping advances as the launches are enqueued.
 int batch_enqueue_streams(wave_batch *b, int nsteps, const float *const *src_dev)
 {
@@ -1721,20 +1733,26 @@ int wave_batch_set_schedule(wave_batch *b, int32_t schedule, int32_t nstreams)
         return bfail(b, WAVE_EHIP, "stream synchronisation failed");
     drop_batch_graph(b);
     drop_streams(b);
-    b->schedule = schedule;
+    b->schedule = 0;
     if (schedule == 1) {
+        // on any failure the batch stays on schedule 0 with no streams
         for (int k = 0; k < nstreams; ++k) {
             hipStream_t st = nullptr;
-            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+                drop_streams(b);
                 return bfail(b, WAVE_EHIP, "stream creation failed");
+            }
             b->aux.push_back(st);
         }
         for (int k = 0; k <= nstreams; ++k) {
             hipEvent_t e = nullptr;
-            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                drop_streams(b);
                 return bfail(b, WAVE_EHIP, "event creation failed");
+            }
             b->ev.push_back(e);
         }
+        b->schedule = 1;
     }
     return WAVE_OK;
 }

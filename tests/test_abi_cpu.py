@@ -130,3 +130,17 @@ def test_misfit_rejects_bad_arguments(w):
 
 def test_check_rejects_null_context(w):
     assert w.lib().wave_check(None, None, None) == w.WAVE_EINVAL
+
+
+def test_batch_calls_reject_null_handles(w):
+    lib = w.lib()
+    out = ctypes.c_void_p(0)
+    assert lib.wave_batch_create(None, None, 1, None, 0) == w.WAVE_EINVAL
+    assert lib.wave_batch_create(ctypes.byref(out), None, 1, None, 0) == w.WAVE_EINVAL
+    assert out.value is None
+    assert lib.wave_batch_run(None, 1, None) == w.WAVE_EINVAL
+    assert lib.wave_batch_set_schedule(None, 1, 2) == w.WAVE_EINVAL
+    assert lib.wave_batch_info(None, None, None, None) == w.WAVE_EINVAL
+    assert lib.wave_batch_sync(None) == w.WAVE_EINVAL
+    assert lib.wave_batch_destroy(None) == w.WAVE_OK
+    assert lib.wave_batch_last_error(None) == b""

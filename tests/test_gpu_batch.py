@@ -215,3 +215,28 @@ def test_per_shot_schedule_matches_individual_runs(wave_mod, nstreams, graph):
     b.close()
     for pr in props:
         pr.close()
+
+
+def test_schedule_switch_and_bad_arguments(wave_mod):
+    shots = make_shots()
+    ref = alone(wave_mod, shots, "f32")
+    props, srcs = build(wave_mod, shots, "f32")
+    b = wave_mod.Batch(props, use_graph=True)
+    for sched, ns in ((1, 0), (1, 17), (2, 1), (-1, 1)):
+        with pytest.raises(wave_mod.WaveError) as e:
+            wave_mod.wave_batch_set_schedule(b.handle, sched, ns)
+        assert e.value.code == wave_mod.WAVE_EINVAL
+    nt = shots[0].nt
+    # every switch drops the captured graph; each run is checked in full
+    for sched, ns in ((1, 2), (0, 1), (1, 4), (1, 4)):
+        print(f"case: schedule {sched}, {ns} streams, graph", flush=True)
+        b.set_schedule(sched, ns)
+        for pr in props:
+            pr.reset()
+        b.run(nt, srcs)
+        b.sync()
+        for i, pr in enumerate(props):
+            assert same(snapshot(pr), ref[i]), (sched, ns, i)
+    b.close()
+    for pr in props:
+        pr.close()
