@@ -290,19 +290,40 @@ int wave_batch_run(wave_batch *b, int32_t nsteps, const float *const *src_dev);
  *               captured graph, replayed while the shots' states, sources,
  *               trace buffers and nsteps repeat.  Shots large enough to
  *               fill the GPU alone run best this way, each with the tiling
- *               that suits its own shape.
- * Both give the same results bit for bit as the shots run alone.  Waits for
+ *               that suits its own shape;
+ *   schedule 2  SWITCHED OFF (returns WAVE_EINVAL): its first GPU run did not
+ *               complete and the cause is not yet known.  Design: FP32
+ *               only; one launch for every step of every shot of a
+ *               group (shots sharing a tile shape), each shot pinned to one
+ *               of the 8 XCDs (largest first to the least loaded) and its
+ *               tiles and chunks started as soon as the ones their stencil
+ *               reads have finished the step before (per-tile step
+ *               counters in place of the launch boundary between steps).
+ *               nstreams is ignored.
+ * All give the same results bit for bit as the shots run alone.  Waits for
  * the batch stream; drops a captured graph.  WAVE_EINVAL for another
  * schedule, a stream count out of range, or schedule 1 with graph replay on
- * the legacy default stream; WAVE_EHIP if the library's streams or events
- * cannot be created, and the batch is then left on schedule 0. */
+ * the legacy default stream, or schedule 2 with shots not stored in FP32;
+ * WAVE_EHIP if the library's streams or events cannot be created and
+ * WAVE_ENOMEM if the schedule-2 tables cannot be allocated; the batch is
+ * then left on schedule 0. */
 int wave_batch_set_schedule(wave_batch *b, int32_t schedule, int32_t nstreams);
+
+/* Schedule 2: how many times one dependency wait polls (about 50 ns apart)
+ * before it gives up; the default is 2^24.  A wait only ever waits for work
+ * already running, so it ends; the limit is a safety net.  A wait that gives
+ * up stops the whole launch, and wave_batch_sync then returns WAVE_EHIP.  A
+ * negative value makes every wait after a launch's first step give up (a
+ * hook for testing that failure path).  Waits for the batch stream and drops
+ * a captured graph. */
+int wave_batch_set_wait_limit(wave_batch *b, int32_t polls);
 
 /* Launch groups, work-groups and interior points of one batched step. */
 int wave_batch_info(const wave_batch *b, int32_t *groups, int64_t *workgroups_per_step,
                     int64_t *points_per_step);
 
-/* Wait for the batch stream; WAVE_EHIP if a batched launch failed. */
+/* Wait for the batch stream; WAVE_EHIP if a batched launch failed or, with
+ * schedule 2, a dependency wait gave up. */
 int wave_batch_sync(wave_batch *b);
 
 int wave_batch_destroy(wave_batch *b);

@@ -72,6 +72,13 @@ __global__ void clear_counters(int *c)
         c[threadIdx.x] = 0;
 }
 
+// Zero n ints (a kernel, not a memset, so that it can sit in a captured graph).
+__global__ __launch_bounds__(256) void zero_ints(int *p, long long n)
+{
+    for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        p[i] = 0;
+}
+
 // Max, min and a non-finite flag of an FP32 k over the interior, as float
 // bit patterns (valid for non-negative values; negatives raise the flag).
 __global__ __launch_bounds__(256) void k_range(const float *__restrict__ k, int nx, int ny, int nz,

@@ -26,12 +26,14 @@ namespace {
 
 typedef void (*StepKernel)(StepArgs);
 typedef void (*BatchKernel)(const ShotDesc *, BatchItems, int);
+typedef void (*FlowKernel)(const ShotDesc *, FlowPlan);
 
 struct Variant {
     const char *name;
     StepKernel fn[kNumKinds];  // by storage type; all NULL for "auto" and "naive"
     BatchKernel batch[3];      // FP32, FP16, BF16 (two-level storage)
     StepKernel adj[3];  // adjoint step, imaging step, fused adjoint + imaging (FP32)
+    FlowKernel flow;    // data-flow batched step (FP32)
     int txv, ty, ry;
 };
 
@@ -41,11 +43,12 @@ struct Variant {
      step_tiled<WAVE_BF16_UV, TXV, TY, RY>},                                                      \
     {step_batch<WAVE_F32, TXV, TY, RY>, step_batch<WAVE_F16, TXV, TY, RY>,                        \
      step_batch<WAVE_BF16, TXV, TY, RY>},                                                         \
-    {adjoint_tiled<kAdj, TXV, TY, RY>, adjoint_tiled<kImg, TXV, TY, RY>, adjoint_tiled<kFus, TXV, TY, RY>}
+    {adjoint_tiled<kAdj, TXV, TY, RY>, adjoint_tiled<kImg, TXV, TY, RY>, adjoint_tiled<kFus, TXV, TY, RY>}, \
+    step_flow<TXV, TY, RY>
 
 const Variant kVariants[] = {
-    {"auto", {nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, 0, 0, 0},
-    {"naive", {nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, 0, 0, 0},
+    {"auto", {nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, nullptr, 0, 0, 0},
+    {"naive", {nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, nullptr, 0, 0, 0},
     {"t64x16_r1", TILED(16, 16, 1), 16, 16, 1},
     {"t128x8_r1", TILED(32, 8, 1), 32, 8, 1},
     {"t128x16_r2", TILED(32, 8, 2), 32, 8, 2},
@@ -700,6 +703,13 @@ struct wave_batch {
         int *d_items = nullptr;       // shot[items], lid[items], xcd_start[9], counters[16]
         BatchItems items{};
         int total = 0, grid = 0, threads = 0;
+        // schedule 2: FlowShot table, xcd_shot[9], xcd_items[8], then the
+        // counters cleared before every launch: tickets[8], done[], abort[1]
+        int *d_flow = nullptr;
+        FlowPlan plan{};
+        int *flow_counters = nullptr;
+        long long flow_ncounters = 0;
+        int flow_grid = 0, flow_max_items = 0;
     };
     std::vector<wave_ctx *> ctx;
     std::vector<int> cfg;  // (variant, zchunk, nwg) of every shot at creation
@@ -710,8 +720,9 @@ struct wave_batch {
     hipGraphExec_t exec = nullptr;
     int graph_steps = -1;
     // schedule 1: every shot launched with its own configuration, shots
-    // dealt round-robin to these streams (fork and join through events)
+    // dealt to these streams (fork and join through events)
     int schedule = 0;
+    int wait_limit = 1 << 24;  // schedule 2: polls before a dependency wait gives up
     std::vector<hipStream_t> aux;
     std::vector<hipEvent_t> ev;  // fork, then one join per stream
     std::vector<int64_t> key;    // the run the graph was captured for
@@ -756,14 +767,134 @@ void drop_streams(wave_batch *b)
     b->ev.clear();
 }
 
+void drop_flow(wave_batch *b)
+{
+    for (auto &g : b->groups) {
+        free_dev(g.d_flow);
+        g.d_flow = nullptr;
+        g.flow_counters = nullptr;
+        g.flow_ncounters = 0;
+    }
+}
+
 void batch_free(wave_batch *b)
 {
     drop_batch_graph(b);
     drop_streams(b);
+    drop_flow(b);
     for (auto &g : b->groups) {
         free_dev(g.d_desc);
         free_dev(g.d_items);
     }
+}
+
+// Schedule 2 is switched off: its first run on the GPU did not complete
+// (no fault; the run exceeded its time limit), and neither a CPU replay of
+// its ticket and dependency logic nor a check of the block-to-XCD mapping
+// found the cause.  set_schedule rejects it until one is found.
+constexpr bool kFlowScheduleEnabled = false;
+
+// Schedule 2 plans: shots dealt to the 8 XCDs, largest first to the least
+// loaded (in cells); per XCD the shots' items of one step, shot by shot.
+int build_flow(wave_batch *b)
+{
+    int device = 0, cus = 0;
+    if (hipGetDevice(&device) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
+        return WAVE_EHIP;
+    for (auto &g : b->groups) {
+        const Variant &V = kVariants[g.variant];
+        const int ns = int(g.shots.size());
+        std::vector<int> order(ns), xcd(ns);
+        std::vector<double> cells(ns);
+        for (int t = 0; t < ns; ++t) {
+            const wave_ctx *c = b->ctx[g.shots[t]];
+            order[t] = t;
+            cells[t] = double(c->p.nx) * c->p.ny * c->p.nz;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cells[x] > cells[y]; });
+        double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (const int t : order) {
+            const int x = int(std::min_element(load, load + 8) - load);
+            load[x] += cells[t];
+            xcd[t] = x;
+        }
+        std::vector<FlowShot> fs;
+        std::vector<int> xcd_shot(9, 0), xcd_items(8, 0);
+        int done = 0;
+        for (int x = 0; x < 8; ++x) {
+            xcd_shot[x] = int(fs.size());
+            for (const int t : order) {
+                if (xcd[t] != x)
+                    continue;
+                const wave_ctx *c = b->ctx[g.shots[t]];
+                FlowShot f{};
+                f.desc = t;
+                f.ntx = c->ntx;
+                f.nty = c->nty;
+                f.nch = (c->p.nz + c->zc_used - 1) / c->zc_used;
+                f.items = f.ntx * f.nty * f.nch;
+                f.base = xcd_items[x];
+                f.done = done;
+                f.zreach = (kGhost + c->zc_used - 1) / c->zc_used;
+                xcd_items[x] += f.items;
+                done += f.items;
+                fs.push_back(f);
+            }
+        }
+        xcd_shot[8] = int(fs.size());
+        // blob: FlowShot table (as ints), xcd_shot, xcd_items, tickets, done, abort
+        static_assert(sizeof(FlowShot) % sizeof(int) == 0, "FlowShot is a whole number of ints");
+        const size_t nfs = fs.size() * (sizeof(FlowShot) / sizeof(int));
+        const long long ncounters = 8 + (long long)done + 1;
+        const size_t nints = nfs + 9 + 8 + size_t(ncounters);
+        free_dev(g.d_flow);
+        g.d_flow = nullptr;
+        if (hipMalloc(&g.d_flow, sizeof(int) * nints) != hipSuccess)
+            return WAVE_ENOMEM;
+        std::vector<int> blob(nfs + 17, 0);
+        std::memcpy(blob.data(), fs.data(), sizeof(FlowShot) * fs.size());
+        std::copy(xcd_shot.begin(), xcd_shot.end(), blob.begin() + nfs);
+        std::copy(xcd_items.begin(), xcd_items.end(), blob.begin() + nfs + 9);
+        if (hipMemcpy(g.d_flow, blob.data(), sizeof(int) * blob.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return WAVE_EHIP;
+        g.plan.shots = reinterpret_cast<const FlowShot *>(g.d_flow);
+        g.plan.xcd_shot = g.d_flow + nfs;
+        g.plan.xcd_items = g.d_flow + nfs + 9;
+        g.flow_counters = g.d_flow + nfs + 17;
+        g.flow_ncounters = ncounters;
+        g.plan.tickets = g.flow_counters;
+        g.plan.done = g.flow_counters + 8;
+        g.plan.abort = g.flow_counters + 8 + done;
+        g.flow_max_items = *std::max_element(xcd_items.begin(), xcd_items.end());
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, V.flow, g.threads, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        g.flow_grid = int(round_up((long long)per_cu * cus, 8));
+    }
+    return WAVE_OK;
+}
+
+// Schedule 2: per group, launches of as many steps as the 32-bit tickets
+// allow (normally the whole run), each after clearing its counters.
+int flow_enqueue(wave_batch *b, int nsteps)
+{
+    for (auto &g : b->groups) {
+        const long long cap = ((1ll << 31) - 1 - g.flow_grid) / std::max(1, g.flow_max_items);
+        const int seg = int(std::max(1ll, std::min<long long>(cap, nsteps)));
+        for (int j0 = 0; j0 < nsteps; j0 += seg) {
+            FlowPlan p = g.plan;
+            p.nsteps = std::min(seg, nsteps - j0);
+            p.j0 = j0;
+            p.wait_limit = b->wait_limit;
+            const int zb = int(std::min<long long>((g.flow_ncounters + 255) / 256, 1024));
+            hipLaunchKernelGGL(zero_ints, dim3(zb), dim3(256), 0, b->stream, g.flow_counters, g.flow_ncounters);
+            hipLaunchKernelGGL(kVariants[g.variant].flow, dim3(g.flow_grid), dim3(g.threads), 0, b->stream,
+                               (const ShotDesc *)g.d_desc, p);
+        }
+    }
+    return hipGetLastError() == hipSuccess ? WAVE_OK : WAVE_EHIP;
 }
 
 // Schedule 1: each shot's steps on one of the K streams with the shot's own kernel;
@@ -1688,7 +1819,7 @@ int wave_batch_run(wave_batch *b, int32_t nsteps, const float *const *src_dev)
                 b->graph_steps = -1;
                 if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
                     return bfail(b, WAVE_EHIP, "graph capture could not start");
-                const int rc = batch_enqueue(b, nsteps);
+                const int rc = b->schedule == 2 ? flow_enqueue(b, nsteps) : batch_enqueue(b, nsteps);
                 hipGraph_t g = nullptr;
                 const hipError_t e = hipStreamEndCapture(b->stream, &g);
                 if (rc != WAVE_OK || e != hipSuccess || !g) {
@@ -1706,7 +1837,7 @@ int wave_batch_run(wave_batch *b, int32_t nsteps, const float *const *src_dev)
             }
             if (hipGraphLaunch(b->exec, b->stream) != hipSuccess)
                 return bfail(b, WAVE_EHIP, "graph launch failed");
-        } else if (batch_enqueue(b, nsteps) != WAVE_OK) {
+        } else if ((b->schedule == 2 ? flow_enqueue(b, nsteps) : batch_enqueue(b, nsteps)) != WAVE_OK) {
             return bfail(b, WAVE_EHIP, "batched launch failed");
         }
     }
@@ -1725,15 +1856,31 @@ int wave_batch_set_schedule(wave_batch *b, int32_t schedule, int32_t nstreams)
 {
     if (!b)
         return WAVE_EINVAL;
-    if (schedule < 0 || schedule > 1 || (schedule == 1 && (nstreams < 1 || nstreams > 16)))
-        return bfail(b, WAVE_EINVAL, "schedule must be 0, or 1 with 1..16 streams");
+    if (schedule < 0 || schedule > 2 || (schedule == 1 && (nstreams < 1 || nstreams > 16)))
+        return bfail(b, WAVE_EINVAL, "schedule must be 0, 1 with 1..16 streams, or 2");
+    if (schedule == 2 && !kFlowScheduleEnabled)
+        return bfail(b, WAVE_EINVAL,
+                     "schedule 2 is switched off: its first GPU run did not complete and the cause is not known");
+    if (schedule == 2)
+        for (const auto &g : b->groups)
+            if (g.kind != WAVE_F32)
+                return bfail(b, WAVE_EINVAL, "schedule 2 runs FP32 shots only");
     if (schedule == 1 && b->use_graph && !b->stream)
         return bfail(b, WAVE_EINVAL, "graph replay needs a stream other than the legacy default stream");
     if (hipStreamSynchronize(b->stream) != hipSuccess)
         return bfail(b, WAVE_EHIP, "stream synchronisation failed");
     drop_batch_graph(b);
     drop_streams(b);
+    drop_flow(b);
     b->schedule = 0;
+    if (schedule == 2) {
+        const int rc = build_flow(b);
+        if (rc != WAVE_OK) {
+            drop_flow(b);
+            return bfail(b, rc, "schedule 2 plan could not be built");
+        }
+        b->schedule = 2;
+    }
     if (schedule == 1) {
         // on any failure the batch stays on schedule 0 with no streams
         for (int k = 0; k < nstreams; ++k) {
@@ -1777,6 +1924,25 @@ int wave_batch_sync(wave_batch *b)
         return WAVE_EINVAL;
     if (hipStreamSynchronize(b->stream) != hipSuccess || hipGetLastError() != hipSuccess)
         return bfail(b, WAVE_EHIP, "batched run failed");
+    if (b->schedule == 2)
+        for (const auto &g : b->groups) {
+            int flag = 0;
+            if (!g.plan.abort || hipMemcpy(&flag, g.plan.abort, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+                return bfail(b, WAVE_EHIP, "schedule 2 status could not be read");
+            if (flag)
+                return bfail(b, WAVE_EHIP, "schedule 2: a dependency wait gave up; the run's results are invalid");
+        }
+    return WAVE_OK;
+}
+
+int wave_batch_set_wait_limit(wave_batch *b, int32_t polls)
+{
+    if (!b)
+        return WAVE_EINVAL;
+    if (hipStreamSynchronize(b->stream) != hipSuccess)
+        return bfail(b, WAVE_EHIP, "stream synchronisation failed");
+    drop_batch_graph(b);  // the limit is a launch argument of the captured graph
+    b->wait_limit = polls;
     return WAVE_OK;
 }
 

@@ -108,6 +108,29 @@ struct BatchItems {
     int *counters;         // [2][8] tickets of the current and the next step
 };
 
+// Data-flow schedule: one launch runs every step of a group of shots.  Each
+// shot is pinned to one XCD; an item is (step, shot, tile, z-chunk).
+struct FlowShot {
+    int desc;            // index into the group's descriptors
+    int items;           // tiles x chunks of the shot
+    int base;            // first item of the shot within its XCD's items of one step
+    int done;            // first completion counter of the shot
+    int ntx, nty, nch;   // tiles in x, in y, and z-chunks
+    int zreach;          // chunks on each side a chunk's 4-plane halo reaches
+};
+
+struct FlowPlan {
+    const FlowShot *shots;  // grouped by XCD
+    const int *xcd_shot;    // [9] FlowShot range of each XCD
+    const int *xcd_items;   // [8] items of one step on each XCD
+    int *tickets;           // [8] next ticket of each XCD (zero at launch)
+    int *done;              // [items of all shots] steps completed (zero at launch)
+    int *abort;             // [1] raised when a wait gives up (zero at launch)
+    int nsteps;             // steps of this launch
+    int j0;                 // step of the run at which this launch starts
+    int wait_limit;         // polls before a wait gives up; < 0: every wait of a step after the first gives up
+};
+
 // Tile shapes (float4 columns x thread rows x rows per thread) of the tiled
 // kernels, in the order of the variant table.
 #define WAVE_TILE_SHAPES(X)                                                                       \

@@ -15,6 +15,8 @@ __global__ __launch_bounds__(TXV *TY) void adjoint_tiled(StepArgs a);
 template <int KIND, int TXV, int TY, int RY>
 __global__ __launch_bounds__(TXV *TY) void step_batch(const ShotDesc *__restrict__ shots, BatchItems it,
                                                        int j);
+template <int TXV, int TY, int RY>
+__global__ __launch_bounds__(TXV *TY) void step_flow(const ShotDesc *__restrict__ shots, FlowPlan p);
 template <int KIND>
 __global__ __launch_bounds__(256) void step_naive(StepArgs a);
 template <int KIND>
@@ -26,6 +28,7 @@ __global__ __launch_bounds__(256) void convert_interior(const void *__restrict__
                                                         int dpx, int dx0, long long dp, float scale,
                                                         const int *exps, int slot);
 __global__ void clear_counters(int *c);
+__global__ __launch_bounds__(256) void zero_ints(int *p, long long n);
 __global__ __launch_bounds__(256) void k_range(const float *__restrict__ k, int nx, int ny, int nz,
                                                int px, int x0, long long plane, unsigned *out);
 __global__ void inject_receivers(float *phi, const float *__restrict__ k,

@@ -51,9 +51,11 @@ __device__ __forceinline__ float src_value(const StepArgs &a)
     return a.src_ptr ? a.src_ptr[0] : a.src_val;
 }
 
-// Work-groups are handed to the 8 XCDs round-robin by block index; map
-// block b to logical work-group (b % 8) * (G / 8) + b / 8 so that each XCD
-// gets a contiguous run of neighbouring tiles whose halos share its L2.
+// Work-groups are handed to the 8 XCDs round-robin by block index (the
+// starting XCD follows on from the previous launch, so blocks with equal
+// b % 8 share an XCD, not necessarily XCD b % 8); map block b to logical
+// work-group (b % 8) * (G / 8) + b / 8 so that each XCD gets a contiguous
+// run of neighbouring tiles whose halos share its L2.
 __device__ __forceinline__ int logical_wg()
 {
     const int b = blockIdx.x;
@@ -130,6 +132,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *field, 
 // keeps the default policy, so it stays resident in L2.
 constexpr int kKeep = 0;
 constexpr int kStream = 2;
+// device scope (sc1): the load misses the CU's L1 and is served by the L2,
+// so it sees what other CUs of the same XCD stored (their stores have
+// reached the L2 before they signal completion)
+constexpr int kCoh = 16;
 
 // Four consecutive cells, decoded to FP32 (times `scale` for 16-bit data).
 template <int KIND, int POL>
@@ -307,7 +313,7 @@ __device__ __forceinline__ void static_for_while(F &&f)
 
 // One work-group's share of a step: the tile and z-chunk numbered `lid`
 // (tiles x fastest, then y, then chunks) of the grid described by `a`.
-template <int KIND, int TXV, int TY, int RY, int MODE = kFwd>
+template <int KIND, int TXV, int TY, int RY, int MODE = kFwd, bool COH = false>
 __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
 {
     constexpr int NT = TXV * TY;
@@ -324,6 +330,9 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
     constexpr bool ADJ = MODE == kAdj || FUS;     // the stencil field is phi, scaled by G on load
     constexpr bool IMG = MODE == kImg;
     static_assert(MODE == kFwd || KIND == WAVE_F32, "adjoint and imaging steps are FP32 only");
+    // load policies of the wave fields (k never changes during a run)
+    constexpr int PK = kKeep | (COH ? kCoh : 0);
+    constexpr int PS = kStream | (COH ? kCoh : 0);
     __shared__ f4 lds[2][LH][LW];
     // second stencil field (the forward level of the imaging term), fused mode only
     __shared__ f4 lds2[FUS ? 2 : 1][FUS ? LH : 1][FUS ? LW : 1];
@@ -466,12 +475,12 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
         const __amdgpu_buffer_rsrc_t rc = plane_rsrc(a.cur, pbytes, z0 - 4 + i);
 #pragma unroll
         for (int r = 0; r < RY; ++r)
-            q[i][r] = load4<KIND, kKeep>(rc, own_ld[r], 1.f);
+            q[i][r] = load4<KIND, PK>(rc, own_ld[r], 1.f);
         if constexpr (FUS) {
             const __amdgpu_buffer_rsrc_t ra = plane_rsrc(a.aux, pbytes, z0 - 4 + i);
 #pragma unroll
             for (int r = 0; r < RY; ++r)
-                q2[i][r] = load4<KIND, kKeep>(ra, own_ld[r], 1.f);
+                q2[i][r] = load4<KIND, PK>(ra, own_ld[r], 1.f);
         }
         if constexpr (ADJ) {
             const float gzi = gz_at(z0 - 4 + i);
@@ -495,22 +504,22 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
         const __amdgpu_buffer_rsrc_t rh = plane_rsrc(a.cur, pbytes, z);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            q[slot][r] = load4<KIND, kKeep>(rq, own_ld[r], 1.f);
-            pv[set][r] = load4<KIND, kStream>(rp, own_in[r], 1.f);
+            q[slot][r] = load4<KIND, PK>(rq, own_ld[r], 1.f);
+            pv[set][r] = load4<KIND, PS>(rp, own_in[r], 1.f);
             kv[set][r] = load4<KIND, kStream>(rk, own_in[r], 1.f);
         }
 #pragma unroll
         for (int h = 0; h < HPT; ++h)
-            hv[set][h] = load4<KIND, kKeep>(rh, h_b[h], 1.f);
+            hv[set][h] = load4<KIND, PK>(rh, h_b[h], 1.f);
         if constexpr (FUS) {
             const __amdgpu_buffer_rsrc_t raq = plane_rsrc(a.aux, pbytes, z + 4);
             const __amdgpu_buffer_rsrc_t rah = plane_rsrc(a.aux, pbytes, z);
 #pragma unroll
             for (int r = 0; r < RY; ++r)
-                q2[slot][r] = load4<KIND, kKeep>(raq, own_ld[r], 1.f);
+                q2[slot][r] = load4<KIND, PK>(raq, own_ld[r], 1.f);
 #pragma unroll
             for (int h = 0; h < HPT; ++h)
-                hv2[set][h] = load4<KIND, kKeep>(rah, h_b[h], 1.f);
+                hv2[set][h] = load4<KIND, PK>(rah, h_b[h], 1.f);
         }
         gzv[set] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(gz_r, 4u * z, 0, 0));
         if constexpr (ADJ)
@@ -822,6 +831,119 @@ __global__ __launch_bounds__(TXV *TY) void step_batch(const ShotDesc *__restrict
     }
 }
 
+
+
+// Schedule 2 (switched off in the host code; see there): every step of
+// every shot of a group in one launch (FP32).
+// A work item is (step j, shot, tile, z-chunk).  The shots are pinned to
+// XCDs (blocks with equal b mod 8 run on one XCD; which one depends on the
+// launches before), so producers and consumers of a
+// shot's fields share one L2; each XCD hands out its items by ticket in
+// step order.  An item of step j starts when its own tile/chunk and the
+// tiles and chunks its stencil reads from have completed step j - 1, which
+// also means none of them still reads the buffer the item overwrites.  A
+// work-group only waits for items with lower tickets, which running
+// work-groups hold, so the waits always end; each wait is still bounded
+// (FlowPlan::wait_limit polls), and a wait that gives up raises the abort
+// flag, on which every work-group stops at its next check.
+
+// Whether every item that item (j, lid) of shot fs depends on has completed
+// step j - 1 (steps counted from the launch's first step).
+__device__ __forceinline__ bool flow_ready(const FlowPlan &p, const FlowShot &fs, int lid, int j)
+{
+    if (j == 0)
+        return true;
+    if (p.wait_limit < 0)  // failure-path hook: every wait gives up
+        return false;
+    const int tiles = fs.ntx * fs.nty;
+    const int tx = lid % fs.ntx, ty = (lid / fs.ntx) % fs.nty, ch = lid / tiles;
+    const int *done = p.done + fs.done;
+    int polls = 0;
+    auto wait_for = [&](int l) -> bool {
+        while (__hip_atomic_load(done + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < j) {
+            if (polls >= p.wait_limit || __hip_atomic_load(p.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                return false;
+            ++polls;
+            __builtin_amdgcn_s_sleep(2);
+        }
+        return true;
+    };
+    const int c0 = max(0, ch - fs.zreach), c1 = min(fs.nch - 1, ch + fs.zreach);
+    for (int c = c0; c <= c1; ++c)
+        if (!wait_for(c * tiles + ty * fs.ntx + tx))
+            return false;
+    const int base = ch * tiles;
+    if (tx > 0 && !wait_for(base + ty * fs.ntx + tx - 1))
+        return false;
+    if (tx + 1 < fs.ntx && !wait_for(base + ty * fs.ntx + tx + 1))
+        return false;
+    if (ty > 0 && !wait_for(base + (ty - 1) * fs.ntx + tx))
+        return false;
+    if (ty + 1 < fs.nty && !wait_for(base + (ty + 1) * fs.ntx + tx))
+        return false;
+    return true;
+}
+
+template <int TXV, int TY, int RY>
+__global__ __launch_bounds__(TXV *TY) void step_flow(const ShotDesc *__restrict__ shots, FlowPlan p)
+{
+    __shared__ int item[3];  // step, FlowShot index, tile/chunk; step < 0: stop
+    const int xcd = blockIdx.x & 7;
+    const int per = p.xcd_items[xcd];
+    const int total = per * p.nsteps;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int j = -1, k = 0, lid = 0;
+            const int t = atomicAdd(&p.tickets[xcd], 1);
+            if (t < total && !__hip_atomic_load(p.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                j = t / per;
+                const int r = t - j * per;
+                k = p.xcd_shot[xcd];
+                while (k + 1 < p.xcd_shot[xcd + 1] && r >= p.shots[k].base + p.shots[k].items)
+                    ++k;
+                lid = r - p.shots[k].base;
+                if (!flow_ready(p, p.shots[k], lid, j)) {
+                    __hip_atomic_store(p.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    j = -1;
+                }
+            }
+            item[0] = j;
+            item[1] = k;
+            item[2] = lid;
+        }
+        __syncthreads();
+        const int j = item[0], k = item[1], lid = item[2];
+        __syncthreads();  // all threads have read the item (and left the LDS of the last one)
+        if (j < 0)
+            break;
+        const FlowShot &fs = p.shots[k];
+        const ShotDesc &d = shots[fs.desc];
+        const int jj = p.j0 + j;  // step within the run
+        StepArgs a = d.a;
+        if (jj & 1) {
+            const void *t = a.cur;
+            a.cur = a.nxt;
+            a.nxt = const_cast<void *>(t);
+        }
+        a.out = a.nxt;  // in place
+        const int n = d.n0 + jj;
+        a.step = n & 0x3fffffff;
+        a.trace_row = d.traces ? d.traces + (size_t)n * d.nrec : nullptr;
+        a.src_ptr = d.src ? d.src + jj : nullptr;
+        a.src_val = 0.f;
+        if (!d.src)
+            a.src_z = -1;
+        tile_step<WAVE_F32, TXV, TY, RY, kFwd, true>(a, lid);
+        // completion: every thread's stores have reached the L2 (the wait
+        // covers stores on this architecture) before the counter moves
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(p.done + fs.done + lid, j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
 
 // One thread per interior cell, every tap read from global memory: a
 // deliberately plain kernel used to cross-check the tiled one.  Same FP32

@@ -91,6 +91,7 @@ def _load():
         "wave_batch_create": ([ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp, i32], ci),
         "wave_batch_run": ([vp, i32, ctypes.POINTER(vp)], ci),
         "wave_batch_set_schedule": ([vp, i32, i32], ci),
+        "wave_batch_set_wait_limit": ([vp, i32], ci),
         "wave_batch_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64)], ci),
         "wave_batch_sync": ([vp], ci),
         "wave_batch_destroy": ([vp], ci),
@@ -278,6 +279,10 @@ def wave_batch_run(b, nsteps: int, src_ptrs=None):
 
 def wave_batch_set_schedule(b, schedule: int, nstreams: int = 1):
     _bcheck(_lib.wave_batch_set_schedule(b, int(schedule), int(nstreams)), b)
+
+
+def wave_batch_set_wait_limit(b, polls: int):
+    _bcheck(_lib.wave_batch_set_wait_limit(b, int(polls)), b)
 
 
 def wave_batch_info(b):
@@ -484,9 +489,16 @@ class Batch:
 
     def set_schedule(self, schedule: int, nstreams: int = 1):
         """0: one persistent launch per step and kernel group; 1: every
-        shot with its own kernel on ``nstreams`` streams."""
+        shot with its own kernel on ``nstreams`` streams; 2 (FP32): one
+        launch per kernel group for the whole run, each shot on one XCD,
+        tiles started as their neighbours finish the previous step."""
         wave_batch_set_schedule(self.handle, schedule, nstreams)
         self.schedule, self.nstreams = int(schedule), int(nstreams)
+
+    def set_wait_limit(self, polls: int):
+        """Schedule 2: polls before a dependency wait gives up (negative:
+        every wait after the first step gives up, to test that path)."""
+        wave_batch_set_wait_limit(self.handle, polls)
 
     def info(self):
         """(launch groups, work-groups per step, interior points per step)"""

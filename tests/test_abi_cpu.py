@@ -140,6 +140,7 @@ def test_batch_calls_reject_null_handles(w):
     assert out.value is None
     assert lib.wave_batch_run(None, 1, None) == w.WAVE_EINVAL
     assert lib.wave_batch_set_schedule(None, 1, 2) == w.WAVE_EINVAL
+    assert lib.wave_batch_set_wait_limit(None, 1) == w.WAVE_EINVAL
     assert lib.wave_batch_info(None, None, None, None) == w.WAVE_EINVAL
     assert lib.wave_batch_sync(None) == w.WAVE_EINVAL
     assert lib.wave_batch_destroy(None) == w.WAVE_OK
