@@ -25,6 +25,12 @@ int probe_copy(const float *src, float *dst, int64_t n, void *stream);
 int probe_read3_write1(const float *a, const float *b, const float *c, float *d, int64_t n,
                        void *stream);
 
+/* o[i] = a[i] + b[i] + c[i] + d[i]; g[i] += o[i] in FP64 (g: n doubles):
+ * four FP32 reads, an FP64 read and write and an FP32 write per element
+ * (36 bytes), the access mix of one fused adjoint-and-imaging update. */
+int probe_adjoint_mix(const float *a, const float *b, const float *c, const float *d, double *g,
+                      float *o, int64_t n, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

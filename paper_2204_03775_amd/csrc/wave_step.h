@@ -130,6 +130,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *field, 
 // u^{n+1} is not read again in the step, so they are streamed
 // non-temporally; u^n is read by the neighbouring tiles as their halo and
 // keeps the default policy, so it stays resident in L2.
+typedef double dv2 __attribute__((ext_vector_type(2)));
+
 constexpr int kKeep = 0;
 constexpr int kStream = 2;
 // device scope (sc1): the load misses the CU's L1 and is served by the L2,
@@ -329,6 +331,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
     constexpr bool FUS = MODE == kFus;            // adjoint step + imaging term of the step after it
     constexpr bool ADJ = MODE == kAdj || FUS;     // the stencil field is phi, scaled by G on load
     constexpr bool IMG = MODE == kImg;
+    constexpr bool GRAD = IMG || FUS;             // adds an imaging term to the FP64 accumulator
     static_assert(MODE == kFwd || KIND == WAVE_F32, "adjoint and imaging steps are FP32 only");
     // load policies of the wave fields (k never changes during a run)
     constexpr int PK = kKeep | (COH ? kCoh : 0);
@@ -538,6 +541,20 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
             const int cur_set = s & 1;
             // next plane (clamped on the last one, whose loads go unused)
             prefetch(min(z + 1, z1 - 1), (s + 9) % QS, cur_set ^ 1);
+            // imaging modes: this plane's accumulator values, loaded before
+            // the arithmetic so that their latency overlaps it; each cell is
+            // read and written once per step, so both are streamed
+            dv2 gacc[GRAD ? RY : 1][2] = {};
+            if constexpr (GRAD) {
+#pragma unroll
+                for (int r = 0; r < RY; ++r)
+                    if (col_full && row_int[r]) {
+                        const dv2 *gp = reinterpret_cast<const dv2 *>(
+                            a.grad + (long long)(z + kGhost) * a.plane + own_in[r] / EB);
+                        gacc[r][0] = __builtin_nontemporal_load(gp);
+                        gacc[r][1] = __builtin_nontemporal_load(gp + 1);
+                    }
+            }
 
             if constexpr (ADJ) {
                 // psi = G phi: the plane that just entered the queue (z + 4)
@@ -693,16 +710,16 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
                 // a full 4-cell group is two aligned 16-byte pairs
                 auto add_grad = [&](const f4 &t) __attribute__((always_inline)) {
                     if (col_full) {
-                        double2 *gp = reinterpret_cast<double2 *>(
-                            a.grad + (long long)(z + kGhost) * a.plane + own_in[r] / EB);
                         if (row_int[r]) {
-                            double2 g0 = gp[0], g1 = gp[1];
+                            dv2 *gp = reinterpret_cast<dv2 *>(a.grad + (long long)(z + kGhost) * a.plane +
+                                                              own_in[r] / EB);
+                            dv2 g0 = gacc[r][0], g1 = gacc[r][1];
                             g0.x += (double)t.v[0];
                             g0.y += (double)t.v[1];
                             g1.x += (double)t.v[2];
                             g1.y += (double)t.v[3];
-                            gp[0] = g0;
-                            gp[1] = g1;
+                            __builtin_nontemporal_store(g0, gp);
+                            __builtin_nontemporal_store(g1, gp + 1);
                         }
                     } else if (row_int[r]) {
                         double *gp = a.grad + (long long)(z + kGhost) * a.plane + own_in[r] / EB;

@@ -27,10 +27,12 @@ def _load():
     lib.probe_copy.restype = ctypes.c_int
     lib.probe_read3_write1.argtypes = [vp, vp, vp, vp, i64, vp]
     lib.probe_read3_write1.restype = ctypes.c_int
+    lib.probe_adjoint_mix.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
+    lib.probe_adjoint_mix.restype = ctypes.c_int
     return lib
 
 
-def measure(n: int, repeats: int = 20) -> dict:
+def measure(n: int, repeats: int = 20, with_adjoint_mix: bool = False) -> dict:
     lib = _load()
     n -= n % 4
     bufs = [torch.rand(n, device="cuda") for _ in range(4)]
@@ -62,8 +64,22 @@ def measure(n: int, repeats: int = 20) -> dict:
     ref = bufs[0] + bufs[1] + bufs[2]
     assert torch.equal(bufs[3], ref) or torch.allclose(bufs[3], ref)
     assert torch.equal(bufs[1], bufs[0])
-    return {"elements": n, "copy_gbs": round(copy_gbs, 1), "copy_us": round(copy_s * 1e6, 2),
-            "read3_write1_gbs": round(r3w1_gbs, 1), "read3_write1_us": round(r3w1_s * 1e6, 2)}
+    out = {"elements": n, "copy_gbs": round(copy_gbs, 1), "copy_us": round(copy_s * 1e6, 2),
+           "read3_write1_gbs": round(r3w1_gbs, 1), "read3_write1_us": round(r3w1_s * 1e6, 2)}
+    if with_adjoint_mix:
+        o = torch.empty(n, device="cuda")
+        g = torch.zeros(n, dtype=torch.float64, device="cuda")
+
+        def adjmix():
+            assert lib.probe_adjoint_mix(ptr[0], ptr[1], ptr[2], ptr[3], g.data_ptr(), o.data_ptr(), n, s) == 0
+
+        adj_gbs, adj_s = timed(adjmix, 36 * n)
+        ref = ((bufs[0] + bufs[1]) + bufs[2]) + bufs[3]
+        assert torch.equal(o, ref)
+        assert torch.allclose(g, (repeats + 1) * ref.double())
+        out.update(adjoint_mix_gbs=round(adj_gbs, 1), adjoint_mix_us=round(adj_s * 1e6, 2))
+        del o, g
+    return out
 
 
 if __name__ == "__main__":
@@ -74,4 +90,4 @@ if __name__ == "__main__":
         from paper_2204_03775_amd import wave
 
         n = wave.wave_layout(512, 512, 512).elems
-    print(json.dumps(measure(n)), flush=True)
+    print(json.dumps(measure(n, with_adjoint_mix=True)), flush=True)
