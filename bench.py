@@ -336,6 +336,10 @@ def gradient_leg(reps: int):
         prop.reset()
         prop.run(p.nt, s)
 
+    def forward_all_levels():
+        prop.reset()
+        prop.forward_checkpointed(p.nt, s, 0)
+
     def gradient(every):
         prop.reset()
         prop.forward_checkpointed(p.nt, s, every)
@@ -356,6 +360,9 @@ def gradient_leg(reps: int):
     info50 = prop.grad_info()
     t_all, (Jall, gall) = timed(gradient, 0)
     info_all = prop.grad_info()
+    # the adjoint pass alone: every level kept, minus the forward run that stores them
+    t_fall, _ = timed(forward_all_levels)
+    t_adj = t_all - t_fall
     wave.wave_set_adjoint_fusion(prop.ctx, False)
     t_sep, (_, gsep) = timed(gradient, 0)
     wave.wave_set_adjoint_fusion(prop.ctx, True)
@@ -365,7 +372,8 @@ def gradient_leg(reps: int):
     log(f"gradient 256^3 x {p.nt}: forward {t_fwd * 1e3:.1f} ms; gradient every {gp.every}: "
         f"{t_g50 * 1e3:.1f} ms ({t_g50 / t_fwd:.2f}x forward); every level kept ({info_all[1]}): "
         f"{t_all * 1e3:.1f} ms ({t_all / t_fwd:.2f}x); two passes per adjoint step: {t_sep * 1e3:.1f} ms; "
-        f"equal: {same} {same_sep}; misfit {J50.item():.6e}")
+        f"equal: {same} {same_sep}; misfit {J50.item():.6e}; adjoint pass {t_adj * 1e3:.1f} ms = "
+        f"{36 * p.points * p.nt / t_adj / 1e9:.0f} GB/s at 36 B/pt")
     finite = bool(torch.isfinite(g50).all().item() and g50.abs().max().item() > 0)
     prop.close()
 
@@ -407,6 +415,9 @@ def gradient_leg(reps: int):
             "all_levels_gb": round(info_all[3] / 1e9, 3),
             "all_levels_over_forward": round(t_all / t_fwd, 3),
             "gradient_ms_all_levels_two_passes": round(t_sep * 1e3, 3),
+            "forward_all_levels_ms": round(t_fall * 1e3, 3),
+            "adjoint_pass_ms": round(t_adj * 1e3, 3),
+            "adjoint_pass_gbs": round(36 * p.points * p.nt / t_adj / 1e9, 1),
             "gradient_gpts_per_s": round(gpts / t_g50, 3),
             "bitwise_equal_across_checkpointing": same, "bitwise_equal_fused_two_passes": same_sep,
             "finite": finite,
@@ -608,10 +619,13 @@ def main() -> int:
     achieved = launch_bytes / kernel_s / 1e9
     traffic = measured_traffic(kname, zchunk) if args.workload == "large_shot" else None
     copy_gbs = None
+    probe_res = {}
     try:
         from paper_2204_03775_amd import probe
 
-        copy_gbs = probe.measure(wave.wave_layout(512, 512, 512).elems, repeats=10)["copy_gbs"]
+        probe_res = probe.measure(wave.wave_layout(512, 512, 512).elems, repeats=10,
+                                  with_adjoint_mix=not args.no_gradient)
+        copy_gbs = probe_res["copy_gbs"]
     except ImportError:
         pass
     log(f"{gpts:.1f} Gpts/s wall, kernel {kernel_s * 1e6:.1f} us/launch = {achieved:.0f} GB/s "
@@ -671,6 +685,9 @@ def main() -> int:
     if not args.no_gradient and args.workload == "large_shot":
         prop.close()
         gradient, grad_crop_out = gradient_leg(max(2, args.steps))
+        mix = probe_res.get("adjoint_mix_gbs")
+        gradient["adjoint_mix_ceiling_gbs"] = mix  # a plain streaming kernel with the same access mix
+        gradient["adjoint_pass_frac_of_mix_ceiling"] = round(gradient["adjoint_pass_gbs"] / mix, 3) if mix else None
         if not (gradient["finite"] and gradient["bitwise_equal_across_checkpointing"]
                 and gradient["bitwise_equal_fused_two_passes"]):
             log("error: gradient not finite or dependent on the checkpoint interval")
