@@ -22,8 +22,10 @@ Parity status per function (what pins it lives in ``tests/test_oracle_*``):
   step_points      pinned against ``run`` (same update, pointwise)
   adjoint          pinned (central finite differences of the misfit computed
                    with ``run``, single cells inside and outside the sponge
-                   and a random direction; dot-product test of the
-                   linearised map)
+                   and a random direction; dot-product identity against
+                   ``tangent`` to FP64 rounding)
+  tangent          pinned (central finite differences of the traces computed
+                   with ``run``, converging as eps^2)
 """
 from __future__ import annotations
 
@@ -77,6 +79,9 @@ def _load():
     lib.oracle_adjoint.argtypes = [ci, ci, ci, cd, cd, cd, ci, cd, dp, ci, dp, ci, ci, ci, ci, ip,
                                    dp, dp, ci]
     lib.oracle_adjoint.restype = ci
+    lib.oracle_tangent.argtypes = [ci, ci, ci, cd, cd, cd, ci, cd, dp, dp, ci, dp, ci, ci, ci, ci, ip,
+                                   dp, ci]
+    lib.oracle_tangent.restype = ci
     _lib = lib
     return lib
 
@@ -199,3 +204,27 @@ def adjoint(k: np.ndarray, h, nt: int, trace_grad, *, s=None, src=(0, 0, 0), rec
     if rc != 0:
         raise ValueError(f"oracle_adjoint rejected its arguments (rc={rc})")
     return grad
+
+
+def tangent(k: np.ndarray, dk: np.ndarray, h, nt: int, *, s=None, src=(0, 0, 0), rec=None,
+            sponge_width: int = 0, sponge_alpha: float = 0.0, nthreads: int | None = None):
+    """Derivative of the traces [nt][nrec] with respect to k along ``dk``
+    (tangent-linear run from zero initial levels; source values fixed)."""
+    k = np.ascontiguousarray(k, dtype=np.float64)
+    dk = np.ascontiguousarray(dk, dtype=np.float64)
+    if dk.shape != k.shape:
+        raise ValueError("dk must have the shape of k")
+    nz, ny, nx = k.shape
+    dx, dy, dz = h
+    rec = np.zeros((0, 3), dtype=np.int32) if rec is None else np.ascontiguousarray(rec, dtype=np.int32).reshape(-1, 3)
+    out = np.zeros((nt, rec.shape[0]), dtype=np.float64)
+    sp = None
+    if s is not None:
+        s = np.ascontiguousarray(s, dtype=np.float64)
+        sp = _dptr(s)
+    rc = _load().oracle_tangent(nx, ny, nz, dx, dy, dz, int(sponge_width), float(sponge_alpha),
+                                _dptr(k), _dptr(dk), int(nt), sp, int(src[0]), int(src[1]), int(src[2]),
+                                rec.shape[0], _iptr(rec), _dptr(out), nthreads or default_threads())
+    if rc != 0:
+        raise ValueError(f"oracle_tangent rejected its arguments (rc={rc})")
+    return out

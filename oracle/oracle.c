@@ -448,3 +448,87 @@ int oracle_adjoint(int nx, int ny, int nz, double dx, double dy, double dz, int 
     free(gx); free(gy); free(gz); free(levels); free(lam); free(w);
     return 0;
 }
+
+/*
+ * Tangent-linear model of oracle_run (zero initial levels, zero ghost
+ * layer): the derivative of the traces with respect to k along dk.
+ * Differentiating the sponge-damped update of Eq. 2,
+ *   a^{n+1} = G (2 a^n - G a^{n-1} + K L a^n) + s_n e_src,
+ * with the source values fixed gives
+ *   da^{n+1} = G (2 da^n - G da^{n-1} + K L da^n + dK L a^n),  da^0 = da^{-1} = 0,
+ * and row n of the result is R da^{n+1} (R samples the receivers).  It is
+ * the linear map whose transpose oracle_adjoint applies.
+ *   dk [nz][ny][nx]; dtraces [nt][nrec] (overwritten).
+ * Returns 0, -1 on invalid arguments, -2 when memory runs out.
+ */
+int oracle_tangent(int nx, int ny, int nz, double dx, double dy, double dz, int sponge_width,
+                   double sponge_alpha, const double *k, const double *dk, int nt, const double *s,
+                   int src_z, int src_y, int src_x, int nrec, const int32_t *rec_zyx,
+                   double *dtraces, int nthreads)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || nt < 0 || !k || !dk || sponge_width < 0)
+        return -1;
+    if (!(dx > 0) || !(dy > 0) || !(dz > 0))
+        return -1;
+    if (s && (src_z < 0 || src_z >= nz || src_y < 0 || src_y >= ny || src_x < 0 || src_x >= nx))
+        return -1;
+    if (nrec < 0 || (nrec > 0 && (!rec_zyx || !dtraces)))
+        return -1;
+    for (int r = 0; r < nrec; ++r) {
+        const int32_t *q = &rec_zyx[3 * r];
+        if (q[0] < 0 || q[0] >= nz || q[1] < 0 || q[1] >= ny || q[2] < 0 || q[2] >= nx)
+            return -1;
+    }
+    if (nthreads < 1)
+        nthreads = 1;
+    double c[5];
+    oracle_coefficients(c);
+    const double idx2 = 1.0 / (dx * dx), idy2 = 1.0 / (dy * dy), idz2 = 1.0 / (dz * dz);
+    const int nxp = nx + 2 * GHOST, nyp = ny + 2 * GHOST, nzp = nz + 2 * GHOST;
+    const size_t npad = (size_t)nxp * nyp * nzp;
+
+    double *gx = malloc(sizeof(double) * (size_t)nx);
+    double *gy = malloc(sizeof(double) * (size_t)ny);
+    double *gz = malloc(sizeof(double) * (size_t)nz);
+    double *buf = calloc(npad * 6, sizeof(double));
+    if (!gx || !gy || !gz || !buf) {
+        free(gx); free(gy); free(gz); free(buf);
+        return -2;
+    }
+    oracle_sponge_profile(nx, sponge_width, sponge_alpha, gx);
+    oracle_sponge_profile(ny, sponge_width, sponge_alpha, gy);
+    oracle_sponge_profile(nz, sponge_width, sponge_alpha, gz);
+    double *prev = buf, *cur = buf + npad, *next = buf + 2 * npad;          /* a */
+    double *dprev = buf + 3 * npad, *dcur = buf + 4 * npad, *dnext = buf + 5 * npad; /* da */
+
+    for (int n = 0; n < nt; ++n) {
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    size_t p = pidx(z, y, x, nyp, nxp);
+                    size_t i = ((size_t)z * ny + y) * nx + x;
+                    double G = gx[x] * gy[y] * gz[z];
+                    double La = lap_at(cur, z, y, x, nyp, nxp, c, idx2, idy2, idz2);
+                    double Lda = lap_at(dcur, z, y, x, nyp, nxp, c, idx2, idy2, idz2);
+                    next[p] = G * (2.0 * cur[p] - G * prev[p] + k[i] * La);
+                    dnext[p] = G * (2.0 * dcur[p] - G * dprev[p] + k[i] * Lda + dk[i] * La);
+                }
+        if (s)
+            next[pidx(src_z, src_y, src_x, nyp, nxp)] += s[n];
+        for (int r = 0; r < nrec; ++r) {
+            const int32_t *q = &rec_zyx[3 * r];
+            dtraces[(size_t)n * nrec + r] = dnext[pidx(q[0], q[1], q[2], nyp, nxp)];
+        }
+        double *t = prev;
+        prev = cur;
+        cur = next;
+        next = t;
+        t = dprev;
+        dprev = dcur;
+        dcur = dnext;
+        dnext = t;
+    }
+    free(gx); free(gy); free(gz); free(buf);
+    return 0;
+}

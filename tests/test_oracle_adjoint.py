@@ -83,3 +83,50 @@ def test_zero_trace_gradient_gives_zero(oracle_lib, case):
     p, k, _ = case
     g = gradient(oracle_lib, p, k, np.zeros((p.nt, len(p.rec))))
     assert np.all(g == 0)
+
+
+def test_tangent_against_central_differences(oracle_lib, case):
+    # the tangent-linear traces are the derivative of the traces along dk:
+    # central differences of two forward runs converge to them as eps^2
+    p, k, _ = case
+    rng = np.random.default_rng(21)
+    dk = rng.standard_normal(k.shape) * k
+    kw = dict(s=p.s, src=p.src, rec=p.rec, sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+    t = oracle_lib.tangent(k, dk, p.h, p.nt, **kw)
+    errs = []
+    for eps in (1e-2, 1e-3, 1e-4, 1e-5):
+        tp = oracle_lib.run(k + eps * dk, p.h, p.nt, **kw)[2]
+        tm = oracle_lib.run(k - eps * dk, p.h, p.nt, **kw)[2]
+        fd = (tp - tm) / (2 * eps)
+        errs.append(np.linalg.norm(fd - t) / np.linalg.norm(t))
+    for a, b in zip(errs, errs[1:]):
+        assert 50 < a / b < 200, errs
+    assert errs[-1] < 1e-9, errs
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_dot_product_identity_with_tangent(oracle_lib, case, seed):
+    # <J dk, w> = <dk, J^T w>: the adjoint is the exact transpose of the
+    # tangent-linear map, so the two sides agree to FP64 rounding
+    p, k, _ = case
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((p.nt, len(p.rec)))
+    dk = rng.standard_normal(k.shape) * k
+    kw = dict(s=p.s, src=p.src, rec=p.rec, sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+    lhs = float(np.sum(oracle_lib.tangent(k, dk, p.h, p.nt, **kw) * w))
+    rhs = float(np.sum(dk * gradient(oracle_lib, p, k, w)))
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs), (lhs, rhs, abs(lhs - rhs) / abs(rhs))
+
+
+def test_tangent_is_linear_and_rejects_bad_shapes(oracle_lib, case):
+    p, k, _ = case
+    rng = np.random.default_rng(8)
+    a, b = rng.standard_normal(k.shape) * k, rng.standard_normal(k.shape) * k
+    kw = dict(s=p.s, src=p.src, rec=p.rec, sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+    ta = oracle_lib.tangent(k, a, p.h, p.nt, **kw)
+    tb = oracle_lib.tangent(k, b, p.h, p.nt, **kw)
+    tab = oracle_lib.tangent(k, 2 * a - 3 * b, p.h, p.nt, **kw)
+    assert np.allclose(tab, 2 * ta - 3 * tb, rtol=1e-12, atol=1e-12 * np.abs(tab).max())
+    assert np.all(oracle_lib.tangent(k, np.zeros_like(k), p.h, p.nt, **kw) == 0)
+    with pytest.raises(ValueError):
+        oracle_lib.tangent(k, k[:-1], p.h, p.nt, **kw)
