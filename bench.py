@@ -176,7 +176,8 @@ def oracle_references(crop_out, grad_out):
 
 def time_shots(prop, p, s, steps, warmup):
     """Run warmup + steps complete shots; return (wall seconds of the timed
-    shots, average step-kernel seconds from HIP events on the stream)."""
+    shots, average step-kernel seconds from HIP events on the stream, and
+    the median shot in seconds from the same events)."""
     import torch
 
     stream = prop.stream
@@ -200,8 +201,9 @@ def time_shots(prop, p, s, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prop.sync()
-    kernel_s = sum(a.elapsed_time(b) for a, b in zip(starts, ends)) / 1e3 / (steps * p.nt)
-    return wall, kernel_s
+    shot_s = sorted(a.elapsed_time(b) / 1e3 for a, b in zip(starts, ends))
+    kernel_s = sum(shot_s) / (steps * p.nt)
+    return wall, kernel_s, shot_s[len(shot_s) // 2]
 
 
 def result_ok(prop) -> bool:
@@ -609,7 +611,7 @@ def main() -> int:
     log(f"kernel {kname}, z-chunk {zchunk}, {nwg} work-groups per step")
     prop.record(p.nt)
     s = torch.tensor(p.s, dtype=torch.float32, device="cuda")
-    wall, kernel_s = time_shots(prop, p, s, args.steps, args.warmup)
+    wall, kernel_s, shot_median = time_shots(prop, p, s, args.steps, args.warmup)
     if not result_ok(prop):
         log("error: non-finite or empty result")
         return 1
@@ -644,7 +646,7 @@ def main() -> int:
             pr.configure(args.variant, args.zchunk)
             v16, zc16, _ = pr.config()
             pr.record(p.nt)
-            w16, k16 = time_shots(pr, p, s, args.steps, args.warmup)
+            w16, k16, _ = time_shots(pr, p, s, args.steps, args.warmup)
             if not result_ok(pr):
                 log(f"error: non-finite or empty {dt} result")
                 return 1
@@ -728,6 +730,8 @@ def main() -> int:
                    "nx": p.nx, "ny": p.ny, "nz": p.nz, "time_steps": p.nt,
                    "kernel": kname, "zchunk": zchunk, "workgroups": nwg,
                    "shots_per_s": round(args.steps / wall, 4),
+                   "median_shot_ms": round(shot_median * 1e3, 3),
+                   "gpts_per_s_median_shot": round(p.points * p.nt / shot_median / 1e9, 3),
                    "paper_tflops_51flop": round(metrics.paper_tflops(gpts), 2),
                    "parallelism": "single GPU",
                    "step_kernel_source_sha256": source_digest(),

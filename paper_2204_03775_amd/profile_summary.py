@@ -60,8 +60,15 @@ def per_kernel(counter_csv: str, counter: str):
     return out
 
 
+# the copy probe's kernel, by its exact name (library kernels such as a
+# "direct_copy_kernel" also contain "copy_k")
+PROBE_COPY = "::copy_k("
+
+
 def pick(d, key):
-    hits = [k for k in d if key in k]
+    """The one key of d whose kernel name (the key, or its first element)
+    contains key."""
+    hits = [k for k in d if key in (k[0] if isinstance(k, tuple) else k)]
     if len(hits) != 1:
         raise SystemExit(f"expected one kernel matching {key!r}, found {hits}")
     return hits[0]
@@ -86,11 +93,11 @@ def traffic(a):
     ws = per_kernel(a.write_step, "WRITE_SIZE")
     fp = per_kernel(a.fetch_probe, "FETCH_SIZE")
     wp = per_kernel(a.write_probe, "WRITE_SIZE")
-    ks, kp = pick(fs, a.match), pick(fp, "copy_k")
+    ks, kp = pick(fs, a.match), pick(fp, PROBE_COPY)
     avg = lambda v: sum(v) / len(v)
     copy_kib = a.probe_elements * 4 / 1024.0  # bytes read (= bytes written) by one copy
     f_scale = copy_kib / avg(fp[kp])
-    w_scale = copy_kib / avg(wp[pick(wp, "copy_k")])
+    w_scale = copy_kib / avg(wp[pick(wp, PROBE_COPY)])
     fetch_b = avg(fs[ks]) * f_scale * 1024
     write_b = avg(ws[pick(ws, a.match)]) * w_scale * 1024
     algo_read, algo_write = 12 * a.points, 4 * a.points
@@ -140,8 +147,8 @@ def kernels(a):
     fp, wp = per(a.fetch_probe, "FETCH_SIZE"), per(a.write_probe, "WRITE_SIZE")
     avg = lambda v: sum(v) / len(v)
     copy_kib = a.probe_elements * 4 / 1024.0
-    f_scale = copy_kib / avg(next(v for k, v in fp.items() if "copy_k" in k[0]))
-    w_scale = copy_kib / avg(next(v for k, v in wp.items() if "copy_k" in k[0]))
+    f_scale = copy_kib / avg(fp[pick(fp, PROBE_COPY)])
+    w_scale = copy_kib / avg(wp[pick(wp, PROBE_COPY)])
     lines = [f"# {a.title}", "",
              f"FETCH_SIZE x {f_scale:.4f} and WRITE_SIZE x {w_scale:.4f} (copy probe, "
              f"{a.probe_elements} floats).  Rows group dispatches by kernel and grid size.", "",
