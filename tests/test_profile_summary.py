@@ -1,0 +1,24 @@
+"""The counter-summary helper picks kernels by exact name fragments; a
+library kernel whose name merely contains the probe's name must not be
+taken for it."""
+import pytest
+
+from paper_2204_03775_amd import profile_summary as ps
+
+
+def test_probe_copy_is_not_confused_with_a_library_copy_kernel():
+    by_grid = {("(anonymous namespace)::copy_k((anonymous namespace)::f4 const*, f4*, long long)", 79872): [1.0],
+               ("void at::native::direct_copy_kernel_cuda(at::TensorIteratorBase&)", 512): [2.0]}
+    assert ps.pick(by_grid, ps.PROBE_COPY)[1] == 79872
+    by_name = {k[0]: v for k, v in by_grid.items()}
+    assert ps.pick(by_name, ps.PROBE_COPY).startswith("(anonymous namespace)::copy_k(")
+
+
+def test_ambiguous_or_missing_matches_fail_loudly():
+    d = {"void wavek::step_tiled<0, 64, 8, 1>(wavek::StepArgs)": [1.0],
+         "void wavek::step_tiled<1, 32, 16, 2>(wavek::StepArgs)": [2.0]}
+    with pytest.raises(SystemExit):
+        ps.pick(d, "step_tiled")
+    with pytest.raises(SystemExit):
+        ps.pick(d, "step_batch")
+    assert ps.pick(d, "step_tiled<0, 64, 8, 1>") in d
