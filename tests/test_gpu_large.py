@@ -5,7 +5,8 @@ configuration the benchmark times (automatic kernel choice).
     (relative L2 <= 1e-5 on the field and the traces);
 (b) the whole 1000-step shot, checked at sampled cells: the oracle
     evaluates step 1000 point by point from the GPU's own u^999, u^998
-    and k, which isolates one step's FP32 rounding at full size."""
+    and k, which isolates one step's FP32 rounding at full size;
+(c) the same sampled check on the paper's largest grid (755 x 994 x 1000)."""
 import numpy as np
 import pytest
 import torch
@@ -141,3 +142,63 @@ def test_full_shot_sampled_16bit(wave_mod, oracle_lib, shot, dtype, eps):
     err = np.abs(got - ref).max()
     print(f"{len(pts)} points: max |diff| {err:.3e} = {err / (eps * M):.2f} eps M")
     assert err <= 8 * eps * M
+
+
+def test_paper_largest_shape_sampled(wave_mod, oracle_lib):
+    # The paper's largest grid, 755 x 994 x 1000 (Table 2), in the launch
+    # configuration the paper-shape leg times: nx is not a multiple of 4
+    # (each row ends in a ragged 4-cell group stored whole) and the plan
+    # makes three rounds of work-groups.  Step nt is evaluated by the oracle
+    # at sampled cells from the GPU's own u^{nt-1}, u^{nt-2}; every cell
+    # past nx (ghost and row padding) must still be zero.
+    nt = 60
+    p = inputs.paper_shape(nt)
+    nz, ny, nx = p.shape
+    kval = np.float32((np.float64(1500.0) * p.dt) ** 2)
+    k = torch.full((1, 1, 1), float(kval), dtype=torch.float32, device="cuda").expand(nz, ny, nx)
+    pr = wave_mod.Propagator(nx, ny, nz, p.h, k, src=p.src, rec=p.rec)
+    del k
+    pr.record(nt)
+    print(f"case: 755x994x1000, {nt} steps, config {pr.config()}", flush=True)
+    s = torch.tensor(p.s, dtype=torch.float32, device="cuda")
+    pr.run(nt - 1, s)
+    pr.sync()
+    cur, prev, _ = pr.fields()
+    u_cur = pr.interior(cur).cpu().numpy()
+    u_prev = pr.interior(prev).cpu().numpy()
+    pr.run(1, s[nt - 1:])
+    pr.sync()
+    new, _, n = pr.fields()
+    assert n == nt
+    x0 = pr.layout.x_offset
+    for b in pr.buf:
+        assert torch.count_nonzero(pr.padded(b)[:, :, x0 + nx:]).item() == 0
+        assert torch.count_nonzero(pr.padded(b)[:, :, :x0]).item() == 0
+    u_new = pr.interior(new).cpu().numpy()
+    tr = pr.traces[:, :pr.nrec].cpu().numpy()
+    assert np.isfinite(tr).all() and np.abs(tr).max() > 0
+    rz, ry, rx = np.asarray(p.rec).T
+    assert np.array_equal(tr[-1], u_new[rz, ry, rx])
+    pr.close()
+
+    rng = np.random.default_rng(755)
+    pts = [rng.integers(0, [nz, ny, nx], size=(20000, 3))]
+    edges_x = sorted({0, 1, 3, 4, nx - 5, nx - 4, nx - 3, nx - 2, nx - 1} |
+                     {e + d for e in range(256, nx, 256) for d in (-1, 0)})
+    edges_y = sorted({0, 3, ny - 1, ny - 4} | {e + d for e in range(8, ny, 8) for d in (-1, 0)})
+    edges_z = sorted({0, 3, nz - 1, nz - 4, 495, 496, 499, 500, 503, 504})
+    for _ in range(4000):
+        pts.append(np.array([[rng.choice(edges_z), rng.choice(edges_y), rng.choice(edges_x)]]))
+    sz, sy, sx = p.src
+    pts.append(np.array([[sz + dz, sy + dy, sx + dx] for dz in range(-4, 5) for dy in range(-4, 5)
+                         for dx in range(-4, 5)]))
+    pts = np.unique(np.concatenate(pts).astype(np.int32), axis=0)
+    k32 = np.broadcast_to(kval, (nz, ny, nx))
+    ref = oracle_lib.step_points(k32, u_cur, u_prev, p.h, pts, src=p.src,
+                                 src_value=float(np.float32(p.s[nt - 1])))
+    got = u_new[pts[:, 0], pts[:, 1], pts[:, 2]].astype(np.float64)
+    scale = np.abs(u_cur).max()
+    err = np.abs(got - ref)
+    print(f"{len(pts)} points: max |diff| {err.max():.3e} (field max {scale:.3e}), rel-L2 {rel(got, ref):.3e}")
+    assert err.max() <= 1e-6 * scale
+    assert rel(got, ref) <= 1e-6
