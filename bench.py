@@ -586,8 +586,8 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        log(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this "
-            "build (the propagator is single-GPU; multi-GPU sharding is a design note only).")
+        log(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the propagator "
+            "is single-GPU; how it would shard across GPUs is a design note only).")
         return 2
 
     import numpy as np

@@ -1,5 +1,5 @@
 """bench.py's command-line contract that needs no GPU: more than one GPU is
-refused with a message (this build runs on one GPU), and the paper's
+refused with a message (the propagator runs on one GPU), and the paper's
 scaling-table figures it prints beside the MI355X rates are the tables'
 own values."""
 import os
