@@ -79,10 +79,33 @@ def apply(props, choice: dict) -> None:
         p.configure(name, zc)
 
 
+def steps_available(prop, src) -> int:
+    """Steps a timing run may take from a reset: bounded by the source
+    values given (the library reads one per step and trusts the caller for
+    the length) and by the trace rows recorded."""
+    n = 1 << 30
+    if src is not None:
+        n = min(n, int(src.numel()))
+    if getattr(prop, "traces", None) is not None and prop.nrec > 0:
+        n = min(n, int(prop.traces.shape[0]))
+    return n
+
+
+def _timed_steps(props, srcs, wanted: int, before: int = 0) -> int:
+    """wanted, capped so that before + steps fit every shot; ValueError when
+    the shots are too short to time at all."""
+    avail = min(steps_available(p, s) for p, s in zip(props, srcs)) - before
+    if avail < 4:
+        raise ValueError(f"too few source values or trace rows to time: {avail + before} steps "
+                         f"available, at least {before + 4} needed")
+    return min(wanted, avail)
+
+
 def time_batch(props, srcs, nsteps: int, stream, schedule: int = 0, nstreams: int = 1) -> float:
     """Seconds per step of one batched run, after a short warm-up; fields
     are reset before and after.  Schedule 0 launches eagerly (one launch per
     step and group); schedule 1 is captured once and the replay is timed."""
+    nsteps = _timed_steps(props, srcs, nsteps)
     b = wave.Batch(props, stream=stream, use_graph=(schedule == 1))
     try:
         if schedule:
@@ -120,10 +143,11 @@ def tune_single(prop, src, stream, nsteps: int = 20, use_cache: bool = True, log
     leaves it configured with that choice and returns it."""
     cache = load_cache() if use_cache else {}
     key = _single_key(prop)
-    if key in cache:
+    if key in cache and cache[key][0] in wave.variants():  # a stale entry is re-tuned
         name, zc = cache[key]
         prop.configure(name, zc)
         return name, zc
+    nsteps = _timed_steps([prop], [src], nsteps, before=3)
     best = None
     for name in VARIANTS:
         for zc in SINGLE_CHUNKS:
@@ -185,7 +209,9 @@ def tune_classes(props, srcs, stream, nsteps: int = 30, use_cache: bool = True, 
                      key=lambda c: -sum(p.points for p in props if size_class(p.nx) == c))
     dtype = props[0].dtype
     cache = load_cache() if use_cache else {}
-    choice = {c: tuple(cache[_key(dtype, c)]) for c in classes if _key(dtype, c) in cache}
+    known = set(wave.variants())
+    choice = {c: tuple(cache[_key(dtype, c)]) for c in classes
+              if _key(dtype, c) in cache and cache[_key(dtype, c)][0] in known}
     todo = [c for c in classes if c not in choice]
     for c in todo:
         choice[c] = DEFAULT
