@@ -299,6 +299,25 @@ def wave_batch_destroy(b):
     _bcheck(_lib.wave_batch_destroy(b))
 
 
+def _indexed(device) -> torch.device:
+    """``device`` with its index made explicit ("cuda" -> "cuda:<current>")."""
+    d = torch.device(device)
+    return torch.device(d.type, torch.cuda.current_device()) if d.type == "cuda" and d.index is None else d
+
+
+def _device_f32(t, n: int, what: str, device) -> int:
+    """Pointer of a contiguous FP32 tensor on ``device`` holding at least
+    ``n`` values.  The library trusts the caller for the length of arrays
+    it reads, so a short one is refused here (explicitly, not by assert)."""
+    if not (isinstance(t, torch.Tensor) and t.dtype == torch.float32 and t.is_cuda and t.is_contiguous()):
+        raise ValueError(f"{what}: a contiguous FP32 device tensor is required")
+    if device is not None and t.device != _indexed(device):
+        raise ValueError(f"{what}: on {t.device}, the fields are on {device}")
+    if t.numel() < n:
+        raise ValueError(f"{what}: {t.numel()} values, {n} needed")
+    return t.data_ptr()
+
+
 def variants() -> dict:
     return {wave_variant_name(i): i for i in range(wave_variant_count())}
 
@@ -319,7 +338,7 @@ class Propagator:
                  u_prev=None):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.h = tuple(float(v) for v in h)
-        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = _indexed(device if device is not None else "cuda")
         self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
         self.layout = wave_layout(self.nx, self.ny, self.nz, self.dtype)
         self.layout32 = wave_layout(self.nx, self.ny, self.nz, WAVE_F32)
@@ -396,21 +415,13 @@ class Propagator:
 
     def run(self, nsteps: int, src=None):
         """``src``: device FP32 tensor with >= nsteps values, or None."""
-        ptr = None
-        if src is not None:
-            assert src.dtype == torch.float32 and src.is_cuda and src.is_contiguous()
-            assert src.numel() >= nsteps
-            ptr = src.data_ptr()
+        ptr = None if src is None else _device_f32(src, int(nsteps), "src", self.device)
         wave_run(self.ctx, int(nsteps), ptr)
 
     def forward_checkpointed(self, nt: int, src=None, every: int = 0):
         """``run`` that also keeps what ``adjoint`` needs (checkpoints every
         ``every`` steps; 0 lets the library choose)."""
-        ptr = None
-        if src is not None:
-            assert src.dtype == torch.float32 and src.is_cuda and src.is_contiguous()
-            assert src.numel() >= nt
-            ptr = src.data_ptr()
+        ptr = None if src is None else _device_f32(src, int(nt), "src", self.device)
         wave_forward_checkpointed(self.ctx, int(nt), ptr, int(every))
 
     def adjoint(self, trace_grad=None, grad=None, accumulate: bool = False):
@@ -418,17 +429,19 @@ class Propagator:
         run, for ``trace_grad`` = dJ/d traces ([nt][nrec] FP32 device)."""
         ptr = None
         if self.nrec > 0:
-            assert trace_grad is not None
+            if trace_grad is None:
+                raise ValueError("trace_grad is required when the shot has receivers")
             nt = wave_grad_info(self.ctx)[0]  # 0 without a run: the library reports it
-            assert trace_grad.dtype == torch.float32 and trace_grad.is_cuda
-            assert trace_grad.is_contiguous()
-            assert nt == 0 or tuple(trace_grad.shape) == (nt, self.nrec)
-            ptr = trace_grad.data_ptr()
+            ptr = _device_f32(trace_grad, nt * self.nrec, "trace_grad", self.device)
+            if nt and tuple(trace_grad.shape) != (nt, self.nrec):
+                raise ValueError(f"trace_grad: shape {tuple(trace_grad.shape)}, expected {(nt, self.nrec)}")
         if grad is None:
             grad = torch.zeros((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
             accumulate = False
-        assert grad.dtype == torch.float64 and grad.is_contiguous()
-        assert tuple(grad.shape) == (self.nz, self.ny, self.nx)
+        if not (grad.dtype == torch.float64 and grad.is_cuda and grad.is_contiguous()
+                and grad.device == self.device and tuple(grad.shape) == (self.nz, self.ny, self.nx)):
+            raise ValueError(f"grad: a contiguous FP64 [{self.nz}][{self.ny}][{self.nx}] tensor on "
+                             f"{self.device} is required")
         wave_adjoint(self.ctx, ptr, grad.data_ptr(), accumulate)
         return grad
 
@@ -513,9 +526,7 @@ class Batch:
                 if t is None:
                     ptrs.append(None)
                 else:
-                    assert t.dtype == torch.float32 and t.is_cuda and t.is_contiguous()
-                    assert t.numel() >= nsteps
-                    ptrs.append(t.data_ptr())
+                    ptrs.append(_device_f32(t, int(nsteps), "srcs", self.props[0].device))
         # order against work on the caller's current stream both ways
         # (field resets before, reads after)
         cur = torch.cuda.current_stream(self.props[0].device)
@@ -541,9 +552,10 @@ class Batch:
 def misfit(traces, observed, stream=None):
     """(0.5 sum (traces - observed)^2 as an FP64 device scalar, FP32
     residual traces - observed), both computed by the library."""
-    assert traces.dtype == torch.float32 and observed.dtype == torch.float32
-    assert traces.is_cuda and traces.is_contiguous() and observed.is_contiguous()
-    assert traces.shape == observed.shape
+    if traces.shape != observed.shape:
+        raise ValueError(f"traces {tuple(traces.shape)} and observed {tuple(observed.shape)} differ")
+    _device_f32(traces, traces.numel(), "traces", None)
+    _device_f32(observed, traces.numel(), "observed", traces.device)
     stream = stream if stream is not None else torch.cuda.current_stream(traces.device)
     out = torch.empty((), dtype=torch.float64, device=traces.device)
     res = torch.empty_like(traces)

@@ -14,9 +14,9 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session")
 def oracle_lib():
+    """The FP64 oracle (built on first load if nothing is built yet)."""
     import oracle
 
-    oracle.build()
     return oracle
 
 
@@ -24,10 +24,10 @@ def oracle_lib():
 def wave_mod():
     """The HIP binding.  Builds the library if nothing is built yet; the
     binding itself raises if the library cannot be loaded."""
-    from paper_2204_03775_amd import wave
-
-    if not os.path.exists(wave.LIB_PATH):
+    if not os.path.exists(os.path.join(ROOT, "paper_2204_03775_amd", "libwave.so")):
         import __graft_entry__
 
         __graft_entry__.build()
+    from paper_2204_03775_amd import wave
+
     return wave

@@ -5,7 +5,8 @@
     bit patterns; the NaN is written from the host, no kernel faults);
   - resume: 100 steps in one run equal, bit for bit, 50 steps, a new
     context started from the saved (u^n, u^{n-1}) and 50 more steps with
-    the source values offset (the oracle's restart is pinned on the CPU)."""
+    the source values offset (the oracle's restart is pinned on the CPU);
+  - the binding refuses source arrays too short or of the wrong type."""
 import numpy as np
 import pytest
 import torch
@@ -86,3 +87,26 @@ def test_resume_is_bitwise(wave_mod, prob):
     assert torch.equal(first, ref[2][:50])
     assert torch.equal(resumed.traces[:p.nt - 50], ref[2][50:])
     resumed.close()
+
+
+def test_binding_refuses_short_or_wrong_arrays(wave_mod, prob):
+    """The library reads source values without knowing the array's length,
+    so the binding refuses what would be read past its end, and arrays of
+    the wrong type, before anything is enqueued."""
+    p = prob
+    prop = make(wave_mod, p)
+    short = torch.zeros(p.nt - 1, dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError, match="needed"):
+        prop.run(p.nt, short)
+    with pytest.raises(ValueError, match="FP32"):
+        prop.run(4, torch.zeros(8, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError, match="FP32"):
+        prop.run(4, torch.zeros(8, dtype=torch.float32))  # host memory
+    with pytest.raises(ValueError, match="needed"):
+        prop.forward_checkpointed(p.nt, short)
+    b = wave_mod.Batch([prop])
+    with pytest.raises(ValueError, match="needed"):
+        b.run(p.nt, [short])
+    b.close()
+    assert wave_mod.wave_fields(prop.ctx)[2] == 0  # nothing ran
+    prop.close()
