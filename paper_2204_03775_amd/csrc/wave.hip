@@ -237,7 +237,8 @@ long long round_workgroups(int kind, int v)
 
 // z-chunk length for a grid of `tiles` x-y tiles and rounds of `cap`
 // work-groups: the chunk count that maximises
-//     nwg / (R cap) * 0.85^(R-1) / (1 + 2/zc),   R = ceil(nwg / cap).
+//     nwg / (R cap) * 0.85^(R-1) / (1 + 2/zc),   R = ceil(nwg / cap)
+// (the maximum is stored in *score when score is not null).
 // The step time follows the rounds the busiest CU runs, so work-group counts
 // just under a multiple of a round are the efficient ones; each further
 // round costs about 15 % beyond its share (idle time at the hand-over), and
@@ -246,7 +247,7 @@ long long round_workgroups(int kind, int v)
 // 16 grids from 112 x 304 x 240 to 600 x 1200 x 200, every chunk count
 // measured, with 128 x 16 tiles; the other large-grid plans it gives are
 // the ones measured best before it.
-int fill_rounds_chunk(long long tiles, int nz, int min_chunk, long long cap)
+int fill_rounds_chunk(long long tiles, int nz, int min_chunk, long long cap, double *score = nullptr)
 {
     double best = -1.0;
     int zc = nz;
@@ -265,7 +266,22 @@ int fill_rounds_chunk(long long tiles, int nz, int min_chunk, long long cap)
             zc = z;
         }
     }
+    if (score)
+        *score = best;
     return zc;
+}
+
+// How well tiles of tx x tyr cells fit an nx x ny plane, for a bandwidth-
+// bound step: the share of x lanes inside the grid, times how even the
+// tiles' work is (mean over tiles / the largest).  A plane one tile wide has
+// idle lanes but equal tiles; a plane with a thin last tile column leaves
+// the CUs that run that column idle at the end of the round.
+double tile_fit(int nx, int ny, int tx, int tyr)
+{
+    const int ntx = (nx + tx - 1) / tx, nty = (ny + tyr - 1) / tyr;
+    const double lanes = double(nx) / (double(ntx) * tx);
+    const double even = (double(nx) / ntx) / std::min(tx, nx) * ((double(ny) / nty) / std::min(tyr, ny));
+    return lanes * even;
 }
 
 Geo plan_geo(int nx, int ny, int nz, int kind, int variant, int zchunk)
@@ -274,9 +290,25 @@ Geo plan_geo(int nx, int ny, int nz, int kind, int variant, int zchunk)
     int v = variant;
     const bool large = (long long)nx * ny * nz >= (1ll << 22);
     // FP32 grids whose x extent leaves more than 5 % of a 256-wide tile's
-    // lanes idle take 128 x 16 tiles
+    // lanes idle ("narrow") choose between 128 x 16 and 256 x 8 tiles by
+    // fit times the chunk rule's round efficiency (128 x 16 on a tie)
     const bool narrow = large && kind == WAVE_F32 && variant == 0 &&
                         double(nx) / (256.0 * ((nx + 255) / 256)) < 0.95;
+    if (narrow && zchunk <= 0) {
+        double best = -1.0;
+        for (const int cand : {kAutoNarrowVariant, kAutoVariant}) {
+            const Variant &C = kVariants[cand];
+            const int tx = 4 * C.txv, tyr = C.ty * C.ry;
+            const long long tiles = (long long)((nx + tx - 1) / tx) * ((ny + tyr - 1) / tyr);
+            double eff = 0.0;
+            (void)fill_rounds_chunk(tiles, nz, kMinChunkNarrow, round_workgroups(kind, cand), &eff);
+            eff *= tile_fit(nx, ny, tx, tyr);
+            if (eff > best * (1.0 + 1e-9)) {
+                best = eff;
+                v = cand;
+            }
+        }
+    }
     if (v == 0)
         v = !large ? kSmallVariant
                    : kind == WAVE_F32 ? (narrow ? kAutoNarrowVariant : kAutoVariant)

@@ -17,6 +17,9 @@ PLANS = {
     (320, 320, 256, "f32"): ("t128x16_r1", 64, 240),      # narrow: 256-wide tiles idle lanes
     (600, 600, 1000, "f32"): ("t128x16_r1", 1000, 190),   # one chunk: a second round costs more
     (400, 400, 400, "f32"): ("t128x16_r1", 80, 500),      # two full rounds beat 78 % of one
+    (200, 200, 1000, "f32"): ("t256x8_r1", 100, 250),     # one tile wide: equal tiles beat 128 x 16
+    (192, 192, 512, "f32"): ("t256x8_r1", 52, 240),
+    (128, 512, 256, "f32"): ("t128x16_r1", 32, 256),      # 128 wide: 256-wide tiles idle half the lanes
     (64, 64, 64, "f32"): ("t64x16_r1", 1, 256),           # small grid: latency-bound plan
 }
 
