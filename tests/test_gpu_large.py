@@ -144,22 +144,27 @@ def test_full_shot_sampled_16bit(wave_mod, oracle_lib, shot, dtype, eps):
     assert err <= 8 * eps * M
 
 
-def test_paper_largest_shape_sampled(wave_mod, oracle_lib):
-    # The paper's largest grid, 755 x 994 x 1000 (Table 2), in the launch
-    # configuration the paper-shape leg times: nx is not a multiple of 4
-    # (each row ends in a ragged 4-cell group stored whole) and the plan
-    # makes three rounds of work-groups.  Step nt is evaluated by the oracle
-    # at sampled cells from the GPU's own u^{nt-1}, u^{nt-2}; every cell
-    # past nx (ghost and row padding) must still be zero.
+@pytest.mark.parametrize("shape", [(755, 994, 1000), (200, 200, 1000)], ids=lambda s: "x".join(map(str, s)))
+def test_paper_shape_sampled(wave_mod, oracle_lib, shape):
+    # The paper's largest and smallest Table 2 grids, in the launch
+    # configuration the paper-shape leg times.  755 x 994 x 1000: nx is not
+    # a multiple of 4 (each row ends in a ragged 4-cell group stored whole)
+    # and the plan makes three rounds of work-groups.  200 x 200 x 1000: one
+    # 256 x 8 tile across, 50 of each row's 64 lanes in the grid, ten
+    # z-chunks.  Step nt is evaluated by the oracle at sampled cells from the
+    # GPU's own u^{nt-1}, u^{nt-2}; every cell past nx (ghost and row
+    # padding) must still be zero.
     nt = 60
-    p = inputs.paper_shape(nt)
+    p = inputs.paper_shape(nt, *shape)
     nz, ny, nx = p.shape
     kval = np.float32((np.float64(1500.0) * p.dt) ** 2)
     k = torch.full((1, 1, 1), float(kval), dtype=torch.float32, device="cuda").expand(nz, ny, nx)
     pr = wave_mod.Propagator(nx, ny, nz, p.h, k, src=p.src, rec=p.rec)
     del k
     pr.record(nt)
-    print(f"case: 755x994x1000, {nt} steps, config {pr.config()}", flush=True)
+    variant, zc, _ = pr.config()
+    tile_x, tile_y = (int(v) for v in wave_mod.wave_variant_name(variant)[1:].split("_")[0].split("x"))
+    print(f"case: {nx}x{ny}x{nz}, {nt} steps, config {pr.config()}", flush=True)
     s = torch.tensor(p.s, dtype=torch.float32, device="cuda")
     pr.run(nt - 1, s)
     pr.sync()
@@ -184,9 +189,9 @@ def test_paper_largest_shape_sampled(wave_mod, oracle_lib):
     rng = np.random.default_rng(755)
     pts = [rng.integers(0, [nz, ny, nx], size=(20000, 3))]
     edges_x = sorted({0, 1, 3, 4, nx - 5, nx - 4, nx - 3, nx - 2, nx - 1} |
-                     {e + d for e in range(256, nx, 256) for d in (-1, 0)})
-    edges_y = sorted({0, 3, ny - 1, ny - 4} | {e + d for e in range(8, ny, 8) for d in (-1, 0)})
-    edges_z = sorted({0, 3, nz - 1, nz - 4, 495, 496, 499, 500, 503, 504})
+                     {e + d for e in range(tile_x, nx, tile_x) for d in (-1, 0)})
+    edges_y = sorted({0, 3, ny - 1, ny - 4} | {e + d for e in range(tile_y, ny, tile_y) for d in (-1, 0)})
+    edges_z = sorted({0, 3, nz - 1, nz - 4} | {e + d for e in range(zc, nz, zc) for d in (-4, -1, 0, 3)})
     for _ in range(4000):
         pts.append(np.array([[rng.choice(edges_z), rng.choice(edges_y), rng.choice(edges_x)]]))
     sz, sy, sx = p.src
