@@ -286,9 +286,10 @@ int wave_batch_run(wave_batch *b, int32_t nsteps, const float *const *src_dev);
  *               configuration, the shots dealt, largest first, to the least
  *               loaded (in cells) of nstreams (1..16) streams of the library
  *               that fork from and join back to the batch stream; with
- *               use_graph the whole run is one
- *               captured graph, replayed while the shots' states, sources,
- *               trace buffers and nsteps repeat.  Shots large enough to
+ *               use_graph each stream's share of the run is captured as a
+ *               graph of its own, replayed on that stream (so the streams
+ *               run concurrently) while the shots' states, sources, trace
+ *               buffers and nsteps repeat.  Shots large enough to
  *               fill the GPU alone run best this way, each with the tiling
  *               that suits its own shape;
  *   schedule 2  SWITCHED OFF (returns WAVE_EINVAL): its first GPU run did not

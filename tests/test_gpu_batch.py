@@ -190,7 +190,9 @@ def test_autotune_choice_is_applied(wave_mod, tmp_path, monkeypatch):
         pr.close()
 
 
-@pytest.mark.parametrize("nstreams,graph", [(1, False), (3, False), (3, True)])
+# 16 streams for 6 shots: streams left without shots are neither forked nor
+# captured
+@pytest.mark.parametrize("nstreams,graph", [(1, False), (3, False), (3, True), (16, True), (16, False)])
 def test_per_shot_schedule_matches_individual_runs(wave_mod, nstreams, graph):
     shots = make_shots()
     ref = alone(wave_mod, shots, "f32")
