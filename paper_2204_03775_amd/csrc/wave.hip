@@ -533,8 +533,10 @@ void free_grad(wave_grad_state &g)
 
 void drop_run_graph(wave_ctx *c)
 {
-    if (c->rg.exec)
+    if (c->rg.exec) {
+        (void)hipStreamSynchronize(c->stream);  // it may still be running
         (void)hipGraphExecDestroy(c->rg.exec);
+    }
     if (c->rg.graph)
         (void)hipGraphDestroy(c->rg.graph);
     c->rg = wave_ctx::RunGraph();
@@ -1903,6 +1905,9 @@ int wave_batch_run(wave_batch *b, int32_t nsteps, const float *const *src_dev)
                 return bfail(b, WAVE_EHIP, "batched launch failed");
             return WAVE_OK;
         }
+        // a replaced graph may still be running: wait before destroying it
+        if (!b->sexec.empty() && hipStreamSynchronize(b->stream) != hipSuccess)
+            return bfail(b, WAVE_EHIP, "stream synchronisation failed");
         drop_batch_graph(b);
         if (capture_stream_graphs(b, nsteps, src_dev) != WAVE_OK) {
             drop_batch_graph(b);
@@ -1943,6 +1948,9 @@ int wave_batch_run(wave_batch *b, int32_t nsteps, const float *const *src_dev)
     if (nsteps > 0) {
         if (b->use_graph) {
             if (b->graph_steps != nsteps) {
+                // a replaced graph may still be running: wait before destroying it
+                if (b->exec && !synced && hipStreamSynchronize(b->stream) != hipSuccess)
+                    return bfail(b, WAVE_EHIP, "stream synchronisation failed");
                 if (b->exec)
                     (void)hipGraphExecDestroy(b->exec);
                 if (b->graph)
