@@ -6,7 +6,8 @@ configuration the benchmark times (automatic kernel choice).
 (b) the whole 1000-step shot, checked at sampled cells: the oracle
     evaluates step 1000 point by point from the GPU's own u^999, u^998
     and k, which isolates one step's FP32 rounding at full size;
-(c) the same sampled check on the paper's largest grid (755 x 994 x 1000)."""
+(c) the same sampled check on the paper's largest and smallest Table 2 grids;
+(d) one step on the largest plane one buffer resource addresses (2 GiB)."""
 import numpy as np
 import pytest
 import torch
@@ -207,3 +208,76 @@ def test_paper_shape_sampled(wave_mod, oracle_lib, shape):
     print(f"{len(pts)} points: max |diff| {err.max():.3e} (field max {scale:.3e}), rel-L2 {rel(got, ref):.3e}")
     assert err.max() <= 1e-6 * scale
     assert rel(got, ref) <= 1e-6
+
+
+def test_maximum_plane_sampled(wave_mod, oracle_lib):
+    # The largest FP32 plane one buffer resource addresses (2 GiB): 23000 x
+    # 23000 cells plus ghosts and row padding, two planes deep.  Seeded
+    # random fields fill the whole grid, so every in-plane byte offset the
+    # kernel forms (up to 2.1e9) carries a value.  One step is checked at
+    # the corners, the source and an interior window by the oracle's
+    # pointwise step on crops of u^n, u^{n-1} (cells at least 4 from a crop
+    # edge that is not a grid edge, so the crop's zero surround is never
+    # read).  FP32 rounding of the update of values |u| <= M stays far
+    # below 32 * 2^-24 * M; an offset error would be of order M.
+    nx = ny = 23000
+    nz = 2
+    L = wave_mod.wave_layout(nx, ny, nz)
+    assert 0.95 * 2 ** 31 < 4 * L.plane < 2 ** 31
+    with pytest.raises(wave_mod.WaveError):
+        wave_mod.wave_layout(nx + 1024, ny, nz)  # a plane past 2 GiB
+    p = inputs.paper_shape(2, nx, ny, nz)
+    kval = np.float32((np.float64(1500.0) * p.dt) ** 2)
+    k = torch.full((1, 1, 1), float(kval), dtype=torch.float32, device="cuda").expand(nz, ny, nx)
+    pr = wave_mod.Propagator(nx, ny, nz, p.h, k, src=p.src, rec=[(0, 0, 0), (nz - 1, ny - 1, nx - 1)])
+    del k
+    pr.record(1)
+    print(f"case: maximum plane {nx}x{ny}x{nz}, config {pr.config()}", flush=True)
+    gen = torch.Generator(device="cuda").manual_seed(2300)
+    for b in pr.buf:
+        pr.interior(b).copy_(torch.rand((nz, ny, nx), generator=gen, device="cuda") - 0.5)
+    cur, prev, _ = pr.fields()
+    sy, sx = p.src[1], p.src[2]
+    windows = [(0, 48, 0, 48), (0, 48, nx - 48, nx), (ny - 48, ny, 0, 48), (ny - 48, ny, nx - 48, nx),
+               (sy - 24, sy + 24, sx - 24, sx + 24), (9001, 9049, 15007, 15055)]
+    crops = [(pr.interior(cur)[:, y0:y1, x0:x1].cpu().numpy(), pr.interior(prev)[:, y0:y1, x0:x1].cpu().numpy())
+             for y0, y1, x0, x1 in windows]
+    s = torch.tensor([np.float32(p.s[0])], dtype=torch.float32, device="cuda")
+    pr.run(1, s)
+    pr.sync()
+    new, _, n = pr.fields()
+    assert n == 1
+    x0p = pr.layout.x_offset
+    tail = pr.padded(new)[:, :, x0p + nx:]
+    assert torch.count_nonzero(tail).item() == 0  # row padding past the last column
+    tr = pr.traces[0, :2].cpu().numpy()
+    errs, refs = [], []
+    M = 0.0
+    for (y0, y1, x0, x1), (uc, up) in zip(windows, crops):
+        got_all = pr.interior(new)[:, y0:y1, x0:x1].cpu().numpy()
+        lo_y = 0 if y0 == 0 else 4
+        hi_y = (y1 - y0) if y1 == ny else (y1 - y0) - 4
+        lo_x = 0 if x0 == 0 else 4
+        hi_x = (x1 - x0) if x1 == nx else (x1 - x0) - 4
+        zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(lo_y, hi_y), np.arange(lo_x, hi_x), indexing="ij")
+        pts = np.stack([zz.ravel(), yy.ravel(), xx.ravel()], axis=1).astype(np.int32)
+        src = None
+        if y0 <= sy < y1 and x0 <= sx < x1:
+            src = (p.src[0], sy - y0, sx - x0)
+        kc = np.broadcast_to(kval, uc.shape)
+        ref = oracle_lib.step_points(kc, uc, up, p.h, pts, src=src, src_value=float(np.float32(p.s[0])))
+        got = got_all[pts[:, 0], pts[:, 1], pts[:, 2]].astype(np.float64)
+        errs.append(np.abs(got - ref))
+        refs.append(ref)
+        M = max(M, float(np.abs(uc).max()), float(np.abs(up).max()))
+        if (y0, x0) == (0, 0):
+            assert tr[0] == got_all[0, 0, 0]
+        if (y1, x1) == (ny, nx):
+            assert tr[1] == got_all[nz - 1, -1, -1]
+    pr.close()
+    err = np.concatenate(errs)
+    ref = np.concatenate(refs)
+    eps = 2.0 ** -24
+    print(f"{err.size} points: max |diff| {err.max():.3e} = {err.max() / (eps * M):.2f} eps M", flush=True)
+    assert err.max() <= 32 * eps * M
+    assert np.linalg.norm(err) / np.linalg.norm(ref) <= 1e-6
