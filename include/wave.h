@@ -261,8 +261,9 @@ int wave_misfit(const float *traces_dev, const float *observed_dev, int64_t n, f
  *   stream     the stream of every batched run (the contexts' own streams
  *              are not used by it); required when use_graph != 0, and then
  *              it must not be the legacy default stream;
- *   use_graph  capture a run's launches once as a HIP graph and replay it
- *              for later runs of the same length.
+ *   use_graph  capture a run's launches once as a HIP graph (schedule 1:
+ *              one graph per stream) and replay it for later runs of the
+ *              same length.
  * The batch holds pointers to the contexts: destroy it before them.
  */
 typedef struct wave_batch wave_batch;
