@@ -11,6 +11,13 @@
   python -m paper_2204_03775_amd.profile_summary counters --csv C --title T --command CMD --out F
       per-kernel averages of any counter set (LDS bank conflicts, issue);
 
+  python -m paper_2204_03775_amd.profile_summary overlap --trace T --match M \
+      --window LABEL,FIRST,COUNT [...] --command CMD --out FILE.md
+      how much the dispatches of a window (matching kernels in time order,
+      FIRST < 0 counting from the end) ran at the same time: hardware
+      queues used, busy time over wall time, share of the time with two or
+      more running;
+
   python -m paper_2204_03775_amd.profile_summary traffic \\
       --fetch-step F --write-step W --fetch-probe PF --write-probe PW \\
       --kernel NAME --zchunk ZC --points N --commands CMDS --out-json J --out-md M
@@ -85,6 +92,47 @@ def stats(prefix: str, command: str, out: str):
                      f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                      f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
     open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def overlap_of(rows):
+    """(dispatches, hardware queues, summed durations, wall span, time with
+    two or more dispatches running), times in ns, of kernel-trace rows."""
+    ev = []
+    for r in rows:
+        ev.append((int(r["Start_Timestamp"]), 1))
+        ev.append((int(r["End_Timestamp"]), -1))
+    ev.sort()  # at equal times an end (-1) comes before a start
+    active, last, multi = 0, None, 0
+    for t, d in ev:
+        if last is not None and active >= 2:
+            multi += t - last
+        active += d
+        last = t
+    busy = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows)
+    span = (ev[-1][0] - ev[0][0]) if ev else 0
+    return len(rows), len({r["Queue_Id"] for r in rows}), busy, span, multi
+
+
+def overlap(a):
+    rows = [r for r in csv.DictReader(open(a.trace)) if a.match in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    lines = ["# Concurrency of kernel dispatches (rocprofv3 kernel trace)", "",
+             f"Command: `{a.command}`", "",
+             f"Dispatches of kernels matching `{a.match}`, in start order; a window is "
+             "(first, count), first < 0 counting from the end.", "",
+             "| window | first, count | dispatches | hardware queues | busy ms | wall ms | busy / wall | "
+             "share of wall with >= 2 running |",
+             "|---|---|---:|---:|---:|---:|---:|---:|"]
+    for spec in a.window:
+        label, first, count = spec.rsplit(",", 2)
+        first, count = int(first), int(count)
+        start = first if first >= 0 else len(rows) + first
+        w = rows[start:start + count]
+        n, q, busy, span, multi = overlap_of(w)
+        lines.append(f"| {label} | {first}, {count} | {n} | {q} | {busy / 1e6:.1f} | {span / 1e6:.1f} | "
+                     f"{busy / max(span, 1):.2f} | {multi / max(span, 1):.2f} |")
+    open(a.out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 
@@ -217,8 +265,14 @@ def main():
     for name in ("csv", "out", "title", "command"):
         c.add_argument("--" + name, required=True)
     c.add_argument("--match", default="wavek::")
+    o = sub.add_parser("overlap")
+    for name in ("trace", "match", "command", "out"):
+        o.add_argument("--" + name, required=True)
+    o.add_argument("--window", action="append", required=True, help="LABEL,FIRST,COUNT")
     a = ap.parse_args()
-    if a.cmd == "counters":
+    if a.cmd == "overlap":
+        overlap(a)
+    elif a.cmd == "counters":
         counters(a)
     elif a.cmd == "stats":
         stats(a.prefix, a.command, a.out)

@@ -22,3 +22,14 @@ def test_ambiguous_or_missing_matches_fail_loudly():
     with pytest.raises(SystemExit):
         ps.pick(d, "step_batch")
     assert ps.pick(d, "step_tiled<0, 64, 8, 1>") in d
+
+
+def test_overlap_counts_concurrent_time():
+    # two queues: [0, 10) and [5, 20) overlap for 5 ns; then [20, 30) alone
+    rows = [{"Start_Timestamp": "0", "End_Timestamp": "10", "Queue_Id": "1"},
+            {"Start_Timestamp": "5", "End_Timestamp": "20", "Queue_Id": "2"},
+            {"Start_Timestamp": "20", "End_Timestamp": "30", "Queue_Id": "1"}]
+    n, q, busy, span, multi = ps.overlap_of(rows)
+    assert (n, q, busy, span, multi) == (3, 2, 35, 30, 5)
+    # back to back on one queue: no overlap
+    assert ps.overlap_of(rows[:1] + rows[2:])[4] == 0
