@@ -15,7 +15,9 @@ Parity status per function (what pins it lives in ``tests/test_oracle_*``):
   laplacian        pinned (polynomial exactness, degree-10 error, convergence,
                    Kronecker-sum brute force)
   run              pinned (impulse response, plane-wave dispersion, energy,
-                   reciprocity, brute force, restart equivalence)
+                   reciprocity, brute force, restart equivalence; the sponge
+                   damping both time levels: on one cell u^{n+1} = G^n w^{n+1},
+                   w the undamped recurrence)
   sponge_profile   parity unpinned beyond W = 0 reduction and its own
                    definition (the sponge is a chosen published method, not
                    something the paper fixes)

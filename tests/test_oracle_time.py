@@ -202,6 +202,31 @@ def test_sponge_profile_definition(oracle_lib):
     assert np.all(oracle_lib.sponge_profile(17, 0, 0.3) == 1.0)
 
 
+def test_sponge_damps_both_time_levels(oracle_lib):
+    # On a one-cell grid (zero ghosts all round) the Laplacian is its centre
+    # term alone, so the scheme is the scalar recurrence
+    #     u^{n+1} = G ((2 + K lam) u^n - G u^{n-1}) + s_n,
+    # G the product of the three axis factors.  With one source value at
+    # step 0, damping both time levels by G gives u^{n+1} = G^n w^{n+1}, w
+    # the undamped solution: trace row n of the sponge run is G^n times that
+    # of the plain run.  Damping only the new level, or only the old one,
+    # breaks this identity.
+    h = (10.0, 12.0, 9.0)
+    k = np.full((1, 1, 1), 7.0)
+    s = np.zeros(40)
+    s[0] = 1.0
+    alpha, width = 0.37, 1
+    plain = oracle_lib.run(k, h, 40, s=s, src=(0, 0, 0), rec=[(0, 0, 0)])[2][:, 0]
+    damped = oracle_lib.run(k, h, 40, s=s, src=(0, 0, 0), rec=[(0, 0, 0)], sponge_width=width,
+                            sponge_alpha=alpha)[2][:, 0]
+    g = oracle_lib.sponge_profile(1, width, alpha)[0] ** 3
+    n = np.arange(40)
+    assert np.abs(plain).max() > 0.5  # an oscillation, not a decay to zero
+    np.testing.assert_allclose(damped, g ** n * plain, rtol=1e-12, atol=1e-14)
+    # the profile's value there: the face cell of a one-cell strip
+    assert g == pytest.approx(math.exp(-3 * (alpha * width) ** 2), rel=1e-14)
+
+
 def test_sponge_width_zero_is_plain_scheme(oracle_lib):
     rng = np.random.default_rng(2)
     k = rng.uniform(1.0, 3.0, size=(10, 11, 12))
