@@ -125,6 +125,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *field, 
                                              kRsrcWord3);
 }
 
+// The same for a plane the stencil may reach outside the grid (z < 0 or
+// z >= nz): a ghost plane gets an empty resource, so its loads return the
+// zeros it holds without reading memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t stencil_plane_rsrc(const void *field, long long plane_bytes,
+                                                                    int z, int nz)
+{
+    const char *p = reinterpret_cast<const char *>(field) + (long long)(z + kGhost) * plane_bytes;
+    const int size = (z >= 0 && z < nz) ? (int)plane_bytes : 0;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), (short)0, size, kRsrcWord3);
+}
+
 // Cache policy of a buffer access (gfx950 encoding of the aux operand):
 // bit 1 = non-temporal.  u^{n-1} and k are read exactly once per step and
 // u^{n+1} is not read again in the step, so they are streamed
@@ -363,9 +374,10 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
         fd = fold_scales(a.c, sc, a.k_scale);
     }
 
-    // A 4-cell column may be read when it lies in [-1, nxq]: allocated and
-    // either interior, ghost or (beyond nx + 3) never used by an interior cell.
-    const bool col_load = xq <= a.nxq;
+    // Only 4-cell groups holding interior cells are read (the ragged last
+    // group's right-ghost lanes with them); ghost rows, columns and planes
+    // hold zero, and their loads are masked so that they return zero without
+    // reading memory.
     const bool col_interior = x < a.nx;
     const bool col_full = x + 3 < a.nx;
 
@@ -378,8 +390,8 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
         row[r] = y0 + ly * RY + r;
         row_int[r] = col_interior && row[r] < a.ny;
         const unsigned b = EB * unsigned((row[r] + kGhost) * a.px + a.x0 + x);
-        own_ld[r] = (col_load && row[r] < a.ny + kGhost) ? b : kOff;
         own_in[r] = row_int[r] ? b : kOff;
+        own_ld[r] = own_in[r];
     }
 
     // halo items of this thread
@@ -402,7 +414,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
         h_lds[h] = use ? (hr + 4) * LW + (hc + 1) : -1;
         const int gy = y0 + hr;
         const int gq = xq0 + hc;
-        const bool ok = use && gy >= -kGhost && gy < a.ny + kGhost && gq >= -1 && gq <= a.nxq;
+        const bool ok = use && gy >= 0 && gy < a.ny && gq >= 0 && gq < a.nxq;
         h_b[h] = ok ? EB * unsigned((gy + kGhost) * a.px + a.x0 + 4 * gq) : kOff;
     }
     // adjoint: sponge factor g_x g_y of every cell this thread loads
@@ -475,12 +487,12 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
     f4 q2[FUS ? QS : 1][RY];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const __amdgpu_buffer_rsrc_t rc = plane_rsrc(a.cur, pbytes, z0 - 4 + i);
+        const __amdgpu_buffer_rsrc_t rc = stencil_plane_rsrc(a.cur, pbytes, z0 - 4 + i, a.nz);
 #pragma unroll
         for (int r = 0; r < RY; ++r)
             q[i][r] = load4<KIND, PK>(rc, own_ld[r], 1.f);
         if constexpr (FUS) {
-            const __amdgpu_buffer_rsrc_t ra = plane_rsrc(a.aux, pbytes, z0 - 4 + i);
+            const __amdgpu_buffer_rsrc_t ra = stencil_plane_rsrc(a.aux, pbytes, z0 - 4 + i, a.nz);
 #pragma unroll
             for (int r = 0; r < RY; ++r)
                 q2[i][r] = load4<KIND, PK>(ra, own_ld[r], 1.f);
@@ -501,7 +513,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
     f4 hv2[FUS ? 2 : 1][FUS ? HPT : 1];
     float gzv[2], gzq[2];  // g_z of the plane and (adjoint) of the queue plane z + 4
     auto prefetch = [&](int z, int slot, int set) {
-        const __amdgpu_buffer_rsrc_t rq = plane_rsrc(a.cur, pbytes, z + 4);
+        const __amdgpu_buffer_rsrc_t rq = stencil_plane_rsrc(a.cur, pbytes, z + 4, a.nz);
         const __amdgpu_buffer_rsrc_t rp = plane_rsrc(UV ? a.dlt : a.nxt, pbytes, z);
         const __amdgpu_buffer_rsrc_t rk = plane_rsrc(a.k, pbytes, z);
         const __amdgpu_buffer_rsrc_t rh = plane_rsrc(a.cur, pbytes, z);
@@ -515,7 +527,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
         for (int h = 0; h < HPT; ++h)
             hv[set][h] = load4<KIND, PK>(rh, h_b[h], 1.f);
         if constexpr (FUS) {
-            const __amdgpu_buffer_rsrc_t raq = plane_rsrc(a.aux, pbytes, z + 4);
+            const __amdgpu_buffer_rsrc_t raq = stencil_plane_rsrc(a.aux, pbytes, z + 4, a.nz);
             const __amdgpu_buffer_rsrc_t rah = plane_rsrc(a.aux, pbytes, z);
 #pragma unroll
             for (int r = 0; r < RY; ++r)
