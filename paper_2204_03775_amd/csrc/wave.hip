@@ -207,8 +207,8 @@ void sponge_profile(int n, int width, double alpha, std::vector<float> &g)
 // step; 128^3: 9.5 against 25.9; 192^3: about 25 against 29).
 constexpr int kAutoVariant = 10;     // t256x8_r1 (FP32)
 constexpr int kAutoNarrowVariant = 6;  // t128x16_r1 (FP32 when 256-wide tiles would idle lanes)
-constexpr int kAuto16Variant = 12;   // t128x32_r2 (FP16 / BF16, two levels)
-constexpr int kAutoUvVariant = 4;    // t128x16_r2 (u-and-change storage)
+constexpr int kAuto16Variant = 4;    // t128x16_r2 (FP16 / BF16, two levels)
+constexpr int kAutoUvVariant = 12;   // t128x32_r2 (u-and-change storage)
 constexpr int kSmallVariant = 2;     // t64x16_r1 for grids of fewer than 2^22 cells
 constexpr int kTargetWorkgroupsSmall = 512;
 constexpr int kMinChunk = 32;

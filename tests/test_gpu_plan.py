@@ -11,8 +11,8 @@ pytestmark = pytest.mark.gpu
 # (nx, ny, nz, dtype): (tile variant, z-chunk, work-groups)
 PLANS = {
     (512, 512, 512, "f32"): ("t256x8_r1", 256, 256),      # one round of 256 x 8 tiles
-    (512, 512, 512, "f16"): ("t128x32_r2", 128, 256),
-    (512, 512, 512, "f16uv"): ("t128x16_r2", 128, 512),   # 256-thread groups, two per CU
+    (512, 512, 512, "f16"): ("t128x16_r2", 128, 512),     # 256-thread groups, two per CU
+    (512, 512, 512, "f16uv"): ("t128x32_r2", 128, 256),
     (755, 994, 1000, "f32"): ("t256x8_r1", 500, 750),     # the paper's largest shape
     (320, 320, 256, "f32"): ("t128x16_r1", 64, 240),      # narrow: 256-wide tiles idle lanes
     (600, 600, 1000, "f32"): ("t128x16_r1", 1000, 190),   # one chunk: a second round costs more
