@@ -35,10 +35,11 @@
  *   Ghost cells must be zero in u fields (zero Dirichlet boundary) and stay
  *   so: the library writes nothing but zero into them (when nx is not a
  *   multiple of 4, a row's last 4-cell group, which ends in right-ghost
- *   cells, is stored whole).  The step kernels take ghost rows, columns and
- *   planes as zero without reading them; only the right-ghost cells inside
- *   a row's last 4-cell group are read, and must hold zero.  x_offset makes
- *   every interior row start on a 128-byte boundary.
+ *   cells, is stored whole).  The tiled step kernels take ghost rows,
+ *   columns and planes as zero without reading them; they read only the
+ *   right-ghost cells inside a row's last 4-cell group, which must hold zero
+ *   (the naive cross-check kernel reads every ghost cell it reaches).
+ *   x_offset makes every interior row start on a 128-byte boundary.
  */
 #ifndef WAVE_H
 #define WAVE_H
