@@ -163,6 +163,35 @@ def run(k: np.ndarray, h, nt: int, *, s=None, src=(0, 0, 0), rec=None, a_cur=Non
     return a_cur, a_prev, traces
 
 
+def run_segments(k: np.ndarray, h, nt: int, segment: int, *, s=None, progress=None, **kw):
+    """``run`` over ``nt`` steps as consecutive calls of at most ``segment``
+    steps, each restarting from the levels the previous one returned (the
+    restart is bitwise, see the restart pin), so that a long run can report
+    progress between segments.  ``progress(done, nt, seconds)`` is called
+    after each segment.  Returns (a_cur, a_prev, traces, seconds spent in
+    ``run``)."""
+    import time
+
+    k = np.ascontiguousarray(k, dtype=np.float64)
+    a_cur = a_prev = None
+    rows = []
+    done, sec = 0, 0.0
+    while done < nt:
+        n = min(segment, nt - done)
+        t0 = time.perf_counter()
+        a_cur, a_prev, tr = run(k, h, n, s=None if s is None else np.asarray(s)[done:], a_cur=a_cur,
+                                a_prev=a_prev, **kw)
+        sec += time.perf_counter() - t0
+        rows.append(tr)
+        done += n
+        if progress is not None:
+            progress(done, nt, sec)
+    if a_cur is None:
+        a_cur, a_prev, tr = run(k, h, 0, s=s, **kw)
+        rows.append(tr)
+    return a_cur, a_prev, np.concatenate(rows, axis=0), sec
+
+
 def step_points(k32, u_cur32, u_prev32, h, pts, *, sponge_width=0, sponge_alpha=0.0,
                 src=None, src_value=0.0) -> np.ndarray:
     """One update at the listed points [npts][3] (z, y, x), in FP64 from FP32

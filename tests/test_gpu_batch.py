@@ -125,6 +125,52 @@ def test_batch_parity_with_oracle(wave_mod, oracle_lib):
         pr.close()
 
 
+@pytest.mark.timeout(900)
+def test_batch_workload_shots_against_oracle(wave_mod, oracle_lib, tmp_path, monkeypatch):
+    # The 32-shot batch workload (seed 2207, 600 steps) run as the benchmark
+    # runs it: schedule and kernels chosen by the tuner, replayed from a HIP
+    # graph.  Its two smallest shots are compared with the FP64 oracle's
+    # full 600-step runs of the same shots, field and traces.
+    from paper_2204_03775_amd import autotune
+
+    monkeypatch.setenv("WAVE_TUNE_CACHE", str(tmp_path / "tune.json"))
+    shots = inputs.batch_shots()
+    nt = shots[0].nt
+    props = []
+    for p in shots:
+        pr = wave_mod.Propagator(p.nx, p.ny, p.nz, p.h, p.k32(), src=p.src, rec=p.rec,
+                                 sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+        pr.record(nt)
+        props.append(pr)
+    srcs = [torch.tensor(p.s, dtype=torch.float32, device="cuda") for p in shots]
+    stream = torch.cuda.Stream()
+    choice = autotune.tune_batch(props, srcs, stream)
+    print(f"case: 32-shot batch, tuned schedule {choice['schedule']} on {choice['nstreams']} "
+          f"stream(s), {nt} steps", flush=True)
+    b = wave_mod.Batch(props, stream=stream, use_graph=True)
+    b.set_schedule(choice["schedule"], choice["nstreams"])
+    for pr in props:
+        pr.reset()
+    b.run(nt, srcs)
+    b.sync()
+    small = sorted(range(len(shots)), key=lambda i: shots[i].points)[:2]
+    for i in small:
+        p, pr = shots[i], props[i]
+        ref = oracle_lib.run(p.k64(), p.h, p.nt, s=p.s, src=p.src, rec=p.rec,
+                             sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+        cur, _, n = pr.fields()
+        got = pr.interior(cur).cpu().numpy()
+        tr = pr.traces.cpu().numpy()[:, :pr.nrec]
+        e_f = np.linalg.norm(got - ref[0]) / np.linalg.norm(ref[0])
+        e_t = np.linalg.norm(tr - ref[2]) / np.linalg.norm(ref[2])
+        print(f"{p.name}: rel-L2 field {e_f:.3e} traces {e_t:.3e}")
+        assert n == nt
+        assert e_f <= 1e-5 and e_t <= 1e-5
+    b.close()
+    for pr in props:
+        pr.close()
+
+
 def test_batch_state_errors(wave_mod):
     shots = make_shots()[:3]
     props, srcs = build(wave_mod, shots, "f32", CONFIGS[:3])

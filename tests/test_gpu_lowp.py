@@ -22,14 +22,23 @@ from paper_2204_03775_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-# measured: f16 2.2e-3 (64^3 field), 1.4e-2 / 5.8e-3 (crop field / traces);
-# bf16 2.5e-2, 0.56 / 0.17 -- two stored time levels at this low Courant
-# number leave the per-step change u^n - u^{n-1} a few 16-bit ulps wide.
-# Storing u^n and the change d^n keeps the change to its own precision:
-# measured f16uv 8.6e-4, 3.1e-3 / 1.7e-3; bf16uv 8.2e-3, 2.5e-2 / 1.4e-2
-# (bounds: about twice the measured values).
-BOUND = {"f16": {"small": 4e-3, "crop": 2e-2}, "bf16": {"small": 4e-2, "crop": 0.8},
-         "f16uv": {"small": 2e-3, "crop": 6e-3}, "bf16uv": {"small": 2e-2, "crop": 5e-2}}
+# Bounds (relative L2 against the FP64 oracle).  u-and-change storage keeps
+# the step change d^n to its own precision; measured f16uv 8.6e-4 (64^3),
+# 3.1e-3 / 1.7e-3 (crop field / traces); bf16uv 8.2e-3, 2.5e-2 / 1.4e-2.
+# Their bounds are about twice the measured values and within the ones
+# proposed for reduced-precision storage (FP16 5e-3, BF16 5e-2).
+# The two-level forms do NOT meet those proposed bounds on the crop: at this
+# Courant number the per-step change u^n - u^{n-1} is only a few 16-bit ulps
+# wide, so rounding each level loses most of it.  Measured f16 2.2e-3
+# (64^3), 1.36e-2 / 5.8e-3 (crop); bf16 2.5e-2, 0.563 / 0.168.  Their crop
+# bounds are regression bounds, about 1.15-1.25x the measured values (an
+# all-zero field scores 1.0, a field off by one stored exponent 1.0 or
+# more), stated separately for the field and the traces.
+BOUND = {"f16": {"small": 4e-3, "crop": (1.6e-2, 7e-3)}, "bf16": {"small": 4e-2, "crop": (0.65, 0.2)},
+         "f16uv": {"small": 2e-3, "crop": (6e-3, 6e-3)}, "bf16uv": {"small": 2e-2, "crop": (5e-2, 5e-2)}}
+# the bounds proposed for reduced-precision storage, which the two-level
+# forms miss on the crop
+PROPOSED = {"f16": 5e-3, "bf16": 5e-2, "f16uv": 5e-3, "bf16uv": 5e-2}
 LOWP = ["f16", "bf16", "f16uv", "bf16uv"]
 
 
@@ -124,8 +133,10 @@ def test_crop_accuracy(wave_mod, crop, crop_ref, dtype):
     f, _, tr, _ = run(wave_mod, crop, dtype)
     e_f, e_t = rel(f, crop_ref[0]), rel(tr, crop_ref[2])
     print(f"{dtype} 128^3 crop x 500: rel-L2 field {e_f:.3e} traces {e_t:.3e}")
-    b = 1e-5 if dtype == "f32" else BOUND[dtype]["crop"]
-    assert e_f <= b and e_t <= b
+    b_f, b_t = (1e-5, 1e-5) if dtype == "f32" else BOUND[dtype]["crop"]
+    assert e_f <= b_f and e_t <= b_t
+    if dtype.endswith("uv"):
+        assert max(e_f, e_t) <= PROPOSED[dtype]
 
 
 def test_f32_export_is_a_copy(wave_mod, ragged):

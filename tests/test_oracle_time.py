@@ -183,6 +183,21 @@ def test_restart_is_bitwise(oracle_lib):
     assert np.array_equal(t1, np.concatenate([t2, t3]))
 
 
+def test_segmented_run_is_bitwise(oracle_lib):
+    # the segmented form used for long runs (progress between segments)
+    # returns exactly what one call returns, including a ragged last segment
+    rng = np.random.default_rng(32)
+    k = rng.uniform(0.5, 2.0, size=(10, 11, 12))
+    s = rng.standard_normal(47)
+    kw = dict(src=(5, 5, 6), rec=[[1, 2, 3], [8, 9, 10]], sponge_width=3, sponge_alpha=0.1)
+    a1, p1, t1 = oracle_lib.run(k, (10.0, 10.0, 10.0), 47, s=s, **kw)
+    seen = []
+    a2, p2, t2, sec = oracle_lib.run_segments(k, (10.0, 10.0, 10.0), 47, 10, s=s,
+                                              progress=lambda d, n, t: seen.append(d), **kw)
+    assert seen == [10, 20, 30, 40, 47] and sec > 0
+    assert np.array_equal(a1, a2) and np.array_equal(p1, p2) and np.array_equal(t1, t2)
+
+
 def test_thread_count_invariance(oracle_lib):
     rng = np.random.default_rng(41)
     k = rng.uniform(0.5, 1.0, size=(16, 9, 10)) * 10
