@@ -210,7 +210,8 @@ int wave_sync(wave_ctx *ctx);
  * as phi = k lambda, so that the adjoint step is the forward stencil update
  * applied to G phi; every forward level a^{m-1} is recomputed segment by
  * segment from checkpoints (a^{c-1}, a^c) taken every C steps, and the sum
- * is accumulated in FP64.  dJ/dv follows as 2 v dt^2 dJ/dk.
+ * is accumulated in FP64.  wave_adjoint_velocity returns dJ/dv = 2 v dt^2
+ * dJ/dk instead.
  */
 
 /* Run nt forward steps from the current state, exactly as wave_run (same
@@ -235,6 +236,33 @@ int wave_forward_checkpointed(wave_ctx *ctx, int32_t nt, const float *src_dev, i
  * field of the layout, kept until wave_destroy.  The context's fields,
  * traces and step counter are left as the forward run left them. */
 int wave_adjoint(wave_ctx *ctx, const float *trace_grad_dev, double *grad_dev, int32_t accumulate);
+
+/* The same adjoint run with the result taken to velocity, for a context
+ * whose k was made from a velocity model v as k = (v dt)^2 (see
+ * wave_velocity_to_k): dJ/dv = 2 dt^2 v dJ/dk.
+ *   v_dev                 FP32 device array [nz][ny][nx] (dense, x
+ *                         fastest): the velocity that gave the context's k;
+ *   dt                    the time step of k = (v dt)^2 (> 0);
+ *   source_scales_with_k  0: the injected source values are held fixed, as
+ *                         in wave_adjoint.  Non-zero: they were k at the
+ *                         source cell times fixed values (Eq. 2 scales the
+ *                         source term by dt^2 V^2 at the source cell), and
+ *                         dJ/dk there gains sum_m lambda^m s_{m-1} / k_src,
+ *                         the derivative through the source values;
+ *   grad_v_dev            FP64 device array [nz][ny][nx]: receives dJ/dv,
+ *                         or has it added when accumulate != 0.
+ * trace_grad_dev, memory, state and errors as for wave_adjoint;
+ * WAVE_EINVAL also for a NULL v_dev or dt <= 0. */
+int wave_adjoint_velocity(wave_ctx *ctx, const float *trace_grad_dev, const float *v_dev, double dt,
+                          int32_t source_scales_with_k, double *grad_v_dev, int32_t accumulate);
+
+/* Eq. 2's per-cell coefficient k = V^2 dt^2 from a velocity model: each of
+ * the n FP32 values of v_dev (device) is multiplied by dt and squared in
+ * FP64, and the result rounded once to FP32 into k_dev (device, n values,
+ * same indexing; the two arrays must not overlap).  Enqueued on `stream`.
+ * WAVE_EINVAL for a NULL pointer, n < 0 or dt <= 0; WAVE_EHIP if the launch
+ * fails. */
+int wave_velocity_to_k(const float *v_dev, int64_t n, double dt, float *k_dev, void *stream);
 
 /* The adjoint run normally makes phi^{m-1} and adds the imaging term of
  * phi^m in one pass over the grid (36 instead of 44 bytes per cell and

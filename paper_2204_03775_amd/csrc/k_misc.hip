@@ -8,17 +8,43 @@ namespace wavek {
 
 // Adds k * trace_grad[row][r] at the receiver cells: one thread per distinct
 // cell, summing its receivers in a fixed order (deterministic, no atomics).
+// With s_val set, the source value of the forward step that made this level
+// is k at the source cell times a fixed wavelet value, so its derivative
+// with respect to that k adds lambda s / k = phi s / k^2 there (lambda =
+// phi / k): thread src_thread takes it -- the thread of the receiver cell
+// that is also the source cell (after its own add), or thread ncells.
 __global__ void inject_receivers(float *phi, const float *__restrict__ k, const long long *__restrict__ cell_off,
                                  const int *__restrict__ cell_start, const int *__restrict__ cell_rec,
-                                 int ncells, const float *__restrict__ tg_row)
+                                 int ncells, const float *__restrict__ tg_row, const float *__restrict__ s_val,
+                                 long long src_off, int src_thread, double *acc)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    float v = 0.f;
     if (c < ncells) {
         float s = 0.f;
         for (int i = cell_start[c]; i < cell_start[c + 1]; ++i)
             s += tg_row[cell_rec[i]];
         const long long o = cell_off[c];
-        phi[o] = fmaf(k[o], s, phi[o]);
+        v = fmaf(k[o], s, phi[o]);
+        phi[o] = v;
+    } else if (c == ncells && s_val) {
+        v = phi[src_off];
+    }
+    if (s_val && c == src_thread) {
+        const double kk = k[src_off];
+        acc[src_off] += (double)v * (double)*s_val / (kk * kk);
+    }
+}
+
+// k = (v dt)^2 per cell, formed in FP64 and rounded once to FP32 (dense
+// [n] arrays).
+__global__ __launch_bounds__(256) void velocity_to_k(const float *__restrict__ v, long long n, double dt,
+                                                    float *k)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double vd = (double)v[i] * dt;
+        k[i] = (float)(vd * vd);
     }
 }
 
@@ -48,10 +74,12 @@ __global__ __launch_bounds__(1024) void misfit_kernel(const float *__restrict__ 
         *out = 0.5 * part[0];
 }
 
-// dense[z][y][x] (+)= acc at the interior cells of the field layout.
+// dense[z][y][x] (+)= acc at the interior cells of the field layout; with
+// v set, the chain rule to velocity: dJ/dv = dJ/dk * 2 dt^2 v (k = (v dt)^2).
 __global__ __launch_bounds__(256) void grad_to_dense(const double *__restrict__ acc, double *dense, int nx,
                                                     int ny, int nz, int px, int x0, long long plane,
-                                                    int accumulate)
+                                                    int accumulate, const float *__restrict__ v,
+                                                    double two_dt2)
 {
     const long long n = (long long)nx * ny * nz;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -59,8 +87,10 @@ __global__ __launch_bounds__(256) void grad_to_dense(const double *__restrict__ 
         const int x = (int)(i % nx);
         const int y = (int)((i / nx) % ny);
         const int z = (int)(i / ((long long)nx * ny));
-        const double v = acc[(long long)(z + kGhost) * plane + (long long)(y + kGhost) * px + x0 + x];
-        dense[i] = accumulate ? dense[i] + v : v;
+        double g = acc[(long long)(z + kGhost) * plane + (long long)(y + kGhost) * px + x0 + x];
+        if (v)
+            g *= two_dt2 * (double)v[i];
+        dense[i] = accumulate ? dense[i] + g : g;
     }
 }
 

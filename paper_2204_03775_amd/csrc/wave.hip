@@ -101,6 +101,7 @@ struct wave_grad_state {
     long long *cell_off = nullptr;
     int *cell_start = nullptr, *cell_rec = nullptr;
     int ncells = -1;
+    std::vector<long long> cell_off_host;  // the cells' offsets, host copy
 };
 
 struct wave_ctx {
@@ -700,6 +701,7 @@ int build_receiver_cells(wave_ctx *c)
     }
     start.push_back(c->nrec);
     g.ncells = int(off.size());
+    g.cell_off_host = off;
     off.resize(std::max<size_t>(off.size(), 1));
     idx.resize(std::max<size_t>(idx.size(), 1));
     HIP_TRY(c, hipMalloc(&g.cell_off, sizeof(long long) * off.size()));
@@ -1556,15 +1558,15 @@ int wave_forward_checkpointed(wave_ctx *ctx, int32_t nt, const float *src_dev, i
     return WAVE_OK;
 }
 
-int wave_adjoint(wave_ctx *ctx, const float *trace_grad_dev, double *grad_dev, int32_t accumulate)
+namespace {
+
+// The adjoint run of the last checkpointed forward run, leaving dJ/dk in the
+// FP64 accumulator g.acc (field layout).  With src_term, the source values
+// are taken to scale with k at the source cell, and their derivative is
+// added there.
+int adjoint_run(wave_ctx *ctx, const float *trace_grad_dev, bool src_term)
 {
-    if (!ctx)
-        return WAVE_EINVAL;
     wave_grad_state &g = ctx->g;
-    if (g.nt < 1)
-        return fail(ctx, WAVE_ESTATE, "wave_adjoint needs a preceding wave_forward_checkpointed");
-    if (!grad_dev || (ctx->nrec > 0 && !trace_grad_dev))
-        return fail(ctx, WAVE_EINVAL, "wave_adjoint: grad and (with receivers) trace_grad are required");
     int rc = build_receiver_cells(ctx);
     if (rc != WAVE_OK)
         return rc;
@@ -1581,14 +1583,28 @@ int wave_adjoint(wave_ctx *ctx, const float *trace_grad_dev, double *grad_dev, i
     HIP_TRY(ctx, hipMemsetAsync(g.phi[1], 0, lb, ctx->stream));
     HIP_TRY(ctx, hipMemsetAsync(g.acc, 0, ab, ctx->stream));
 
+    // the source cell's thread in inject_receivers: the receiver cell that is
+    // also the source cell, else one past the receiver cells
+    src_term = src_term && g.has_src && ctx->src[0] >= 0;
+    long long src_off = 0;
+    int src_thread = g.ncells;
+    if (src_term) {
+        src_off = elem_offset(ctx->lay, ctx->src[0], ctx->src[1], ctx->src[2]);
+        for (int i = 0; i < g.ncells; ++i)
+            if (g.cell_off_host[i] == src_off)
+                src_thread = i;
+    }
+
     const Geo geo = adjoint_geo(ctx);
-    // + K R^T (dJ/d traces, row m-1) into phi^m
+    // + K R^T (dJ/d traces, row m-1) into phi^m (and the source-cell term)
     auto inject = [&](void *phi, int m) -> int {
-        if (g.ncells > 0) {
-            hipLaunchKernelGGL(inject_receivers, dim3((g.ncells + 255) / 256), dim3(256), 0, ctx->stream,
+        const int threads = g.ncells + (src_term ? 1 : 0);
+        if (threads > 0) {
+            hipLaunchKernelGGL(inject_receivers, dim3((threads + 255) / 256), dim3(256), 0, ctx->stream,
                                static_cast<float *>(phi), static_cast<const float *>(ctx->k), g.cell_off,
                                g.cell_start, g.cell_rec, g.ncells,
-                               trace_grad_dev + (size_t)(m - 1) * ctx->nrec);
+                               g.ncells > 0 ? trace_grad_dev + (size_t)(m - 1) * ctx->nrec : nullptr,
+                               src_term ? g.src + (m - 1) : nullptr, src_off, src_thread, g.acc);
             HIP_TRY(ctx, hipGetLastError());
         }
         return WAVE_OK;
@@ -1646,13 +1662,69 @@ int wave_adjoint(wave_ctx *ctx, const float *trace_grad_dev, double *grad_dev, i
                 return rc;
         }
     }
+    return WAVE_OK;
+}
+
+// dJ/dk (v == nullptr) or dJ/dv (k = (v dt)^2) from the accumulator into a
+// dense FP64 array.
+int adjoint_output(wave_ctx *ctx, double *grad_dev, int32_t accumulate, const float *v_dev, double dt)
+{
     const long long n = (long long)ctx->p.nx * ctx->p.ny * ctx->p.nz;
     hipLaunchKernelGGL(grad_to_dense, dim3((unsigned)std::min<long long>((n + 255) / 256, 8192)), dim3(256),
-                       0, ctx->stream, g.acc, grad_dev, ctx->p.nx, ctx->p.ny, ctx->p.nz,
+                       0, ctx->stream, ctx->g.acc, grad_dev, ctx->p.nx, ctx->p.ny, ctx->p.nz,
                        int(ctx->lay.pitch_x), int(ctx->lay.x_offset), (long long)ctx->lay.plane,
-                       accumulate ? 1 : 0);
+                       accumulate ? 1 : 0, v_dev, 2.0 * dt * dt);
     HIP_TRY(ctx, hipGetLastError());
     return WAVE_OK;
+}
+
+int adjoint_checks(wave_ctx *ctx, const float *trace_grad_dev, const double *grad_dev)
+{
+    if (ctx->g.nt < 1)
+        return fail(ctx, WAVE_ESTATE, "the adjoint run needs a preceding wave_forward_checkpointed");
+    if (!grad_dev || (ctx->nrec > 0 && !trace_grad_dev))
+        return fail(ctx, WAVE_EINVAL, "adjoint run: grad and (with receivers) trace_grad are required");
+    return WAVE_OK;
+}
+
+}  // namespace
+
+int wave_adjoint(wave_ctx *ctx, const float *trace_grad_dev, double *grad_dev, int32_t accumulate)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    int rc = adjoint_checks(ctx, trace_grad_dev, grad_dev);
+    if (rc == WAVE_OK)
+        rc = adjoint_run(ctx, trace_grad_dev, false);
+    if (rc == WAVE_OK)
+        rc = adjoint_output(ctx, grad_dev, accumulate, nullptr, 0.0);
+    return rc;
+}
+
+int wave_adjoint_velocity(wave_ctx *ctx, const float *trace_grad_dev, const float *v_dev, double dt,
+                          int32_t source_scales_with_k, double *grad_v_dev, int32_t accumulate)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    if (!v_dev || !(std::isfinite(dt) && dt > 0.0))
+        return fail(ctx, WAVE_EINVAL, "wave_adjoint_velocity: v is required and dt must be > 0");
+    int rc = adjoint_checks(ctx, trace_grad_dev, grad_v_dev);
+    if (rc == WAVE_OK)
+        rc = adjoint_run(ctx, trace_grad_dev, source_scales_with_k != 0);
+    if (rc == WAVE_OK)
+        rc = adjoint_output(ctx, grad_v_dev, accumulate, v_dev, dt);
+    return rc;
+}
+
+int wave_velocity_to_k(const float *v_dev, int64_t n, double dt, float *k_dev, void *stream)
+{
+    if (!v_dev || !k_dev || n < 0 || !(std::isfinite(dt) && dt > 0.0))
+        return WAVE_EINVAL;
+    if (n == 0)
+        return WAVE_OK;
+    hipLaunchKernelGGL(velocity_to_k, dim3((unsigned)std::min<long long>((n + 255) / 256, 8192)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), v_dev, (long long)n, dt, k_dev);
+    return hipGetLastError() == hipSuccess ? WAVE_OK : WAVE_EHIP;
 }
 
 int wave_check(wave_ctx *ctx, int64_t *field_nonfinite, int64_t *trace_nonfinite)

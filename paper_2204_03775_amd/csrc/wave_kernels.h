@@ -34,7 +34,10 @@ __global__ __launch_bounds__(256) void k_range(const float *__restrict__ k, int 
 __global__ void inject_receivers(float *phi, const float *__restrict__ k,
                                  const long long *__restrict__ cell_off,
                                  const int *__restrict__ cell_start, const int *__restrict__ cell_rec,
-                                 int ncells, const float *__restrict__ tg_row);
+                                 int ncells, const float *__restrict__ tg_row, const float *__restrict__ s_val,
+                                 long long src_off, int src_thread, double *acc);
+__global__ __launch_bounds__(256) void velocity_to_k(const float *__restrict__ v, long long n, double dt,
+                                                    float *k);
 __global__ __launch_bounds__(1024) void misfit_kernel(const float *__restrict__ tr,
                                                       const float *__restrict__ obs, long long n,
                                                       float *residual, double *out);
@@ -44,6 +47,7 @@ __global__ __launch_bounds__(256) void count_nonfinite(const void *__restrict__ 
                                                       int *out);
 __global__ __launch_bounds__(256) void grad_to_dense(const double *__restrict__ acc, double *dense, int nx,
                                                     int ny, int nz, int px, int x0, long long plane,
-                                                    int accumulate);
+                                                    int accumulate, const float *__restrict__ v,
+                                                    double two_dt2);
 
 }  // namespace wavek

@@ -82,6 +82,8 @@ def _load():
         "wave_destroy": ([vp], ci),
         "wave_forward_checkpointed": ([vp, i32, vp, i32], ci),
         "wave_adjoint": ([vp, vp, vp, i32], ci),
+        "wave_adjoint_velocity": ([vp, vp, vp, ctypes.c_double, i32, vp, i32], ci),
+        "wave_velocity_to_k": ([vp, i64, ctypes.c_double, vp, vp], ci),
         "wave_set_adjoint_fusion": ([vp, i32], ci),
         "wave_set_graph": ([vp, i32], ci),
         "wave_check": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], ci),
@@ -218,6 +220,16 @@ def wave_forward_checkpointed(ctx, nt: int, src_ptr=None, every: int = 0):
 
 def wave_adjoint(ctx, trace_grad_ptr, grad_ptr, accumulate: bool = False):
     _check(_lib.wave_adjoint(ctx, trace_grad_ptr, grad_ptr, int(bool(accumulate))), ctx)
+
+
+def wave_adjoint_velocity(ctx, trace_grad_ptr, v_ptr, dt: float, source_scales_with_k: bool,
+                          grad_v_ptr, accumulate: bool = False):
+    _check(_lib.wave_adjoint_velocity(ctx, trace_grad_ptr, v_ptr, float(dt), int(bool(source_scales_with_k)),
+                                      grad_v_ptr, int(bool(accumulate))), ctx)
+
+
+def wave_velocity_to_k(v_ptr, n: int, dt: float, k_ptr, stream):
+    _check(_lib.wave_velocity_to_k(v_ptr, int(n), float(dt), k_ptr, stream))
 
 
 def wave_check(ctx):
@@ -445,6 +457,29 @@ class Propagator:
         wave_adjoint(self.ctx, ptr, grad.data_ptr(), accumulate)
         return grad
 
+    def adjoint_velocity(self, trace_grad, v, dt: float, source_scales_with_v: bool = False, grad=None,
+                         accumulate: bool = False):
+        """dJ/dv (FP64 [nz][ny][nx] device tensor) of the last checkpointed
+        run, for a context whose k was made from ``v`` (dense FP32 device)
+        as (v dt)^2; ``source_scales_with_v``: the source values were made
+        with the velocity at the source cell (see wave_adjoint_velocity)."""
+        ptr = None
+        if self.nrec > 0:
+            if trace_grad is None:
+                raise ValueError("trace_grad is required when the shot has receivers")
+            nt = wave_grad_info(self.ctx)[0]
+            ptr = _device_f32(trace_grad, nt * self.nrec, "trace_grad", self.device)
+        vptr = _device_f32(v, self.points, "v", self.device)
+        if grad is None:
+            grad = torch.zeros((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+            accumulate = False
+        if not (grad.dtype == torch.float64 and grad.is_cuda and grad.is_contiguous()
+                and grad.device == self.device and tuple(grad.shape) == (self.nz, self.ny, self.nx)):
+            raise ValueError(f"grad: a contiguous FP64 [{self.nz}][{self.ny}][{self.nx}] tensor on "
+                             f"{self.device} is required")
+        wave_adjoint_velocity(self.ctx, ptr, vptr, dt, source_scales_with_v, grad.data_ptr(), accumulate)
+        return grad
+
     def grad_info(self):
         """(steps, segment length, segments, checkpoint bytes) of the last
         checkpointed run."""
@@ -567,10 +602,13 @@ def misfit(traces, observed, stream=None):
 class Survey:
     """Everything of a shot except the model: grid spacing, time step,
     steps, source position and values, receivers, sponge, checkpoint
-    interval (0: library's choice)."""
+    interval (0: library's choice).  ``source_scales_with_v``: the source
+    values were made with the velocity at the source cell (Eq. 2's
+    dt^2 V^2 f^n, as the workload generators make them), so the gradient
+    includes their dependence on it; otherwise they are held fixed."""
 
     def __init__(self, h, dt, nt, src, src_values, rec, sponge_width=0, sponge_alpha=0.0,
-                 every=0):
+                 every=0, source_scales_with_v=False):
         self.h = tuple(float(v) for v in h)
         self.dt = float(dt)
         self.nt = int(nt)
@@ -580,14 +618,17 @@ class Survey:
         self.sponge_width = int(sponge_width)
         self.sponge_alpha = float(sponge_alpha)
         self.every = int(every)
+        self.source_scales_with_v = bool(source_scales_with_v)
 
 
 class _TracesOfVelocity(torch.autograd.Function):
     @staticmethod
     def forward(ctx, v, survey):
         nz, ny, nx = v.shape
-        dt = survey.dt
-        k = (v.detach().to(torch.float64) * dt).square().to(torch.float32)
+        vv = v.detach().to(torch.float32).contiguous()
+        k = torch.empty_like(vv)
+        stream = torch.cuda.current_stream(vv.device)
+        wave_velocity_to_k(vv.data_ptr(), vv.numel(), survey.dt, k.data_ptr(), stream.cuda_stream)
         prop = Propagator(nx, ny, nz, survey.h, k, src=survey.src, rec=survey.rec,
                           sponge_width=survey.sponge_width, sponge_alpha=survey.sponge_alpha,
                           device=v.device)
@@ -597,20 +638,19 @@ class _TracesOfVelocity(torch.autograd.Function):
             src = torch.as_tensor(src, dtype=torch.float32).to(v.device).contiguous()
         prop.forward_checkpointed(survey.nt, src, survey.every)
         ctx.prop = prop
-        ctx.dt = dt
-        ctx.save_for_backward(v)
+        ctx.survey = survey
+        ctx.v = vv
+        ctx.v_dtype = v.dtype
         return prop.traces[:, :prop.nrec].clone()
 
     @staticmethod
     def backward(ctx, g):
-        (v,) = ctx.saved_tensors
-        prop = ctx.prop
+        prop, survey = ctx.prop, ctx.survey
         g = g.to(torch.float32).contiguous()
-        grad_k = prop.adjoint(g)
-        grad_v = grad_k * (2.0 * ctx.dt * ctx.dt) * v.detach().to(torch.float64)
+        grad_v = prop.adjoint_velocity(g if prop.nrec else None, ctx.v, survey.dt, survey.source_scales_with_v)
         prop.close()
         ctx.prop = None
-        return grad_v.to(v.dtype), None
+        return grad_v.to(ctx.v_dtype), None
 
 
 def traces_of_velocity(v, survey: Survey):

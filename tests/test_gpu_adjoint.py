@@ -330,3 +330,115 @@ def test_full_size_directional_derivative(wave_mod):
     print(f"J {J.item():.6e}; <dJ/dk, dk> {an:.6e}, central difference {fd:.6e}")
     assert np.isfinite(g).all()
     assert abs(an - fd) <= 2e-2 * abs(fd)
+
+
+def test_velocity_to_k_rounds_once(wave_mod):
+    # k = (v dt)^2 formed in FP64 and rounded once to FP32, bit for bit
+    rng = np.random.default_rng(7)
+    v = rng.uniform(1400.0, 4700.0, size=100003).astype(np.float32)
+    dt = 0.805076e-3
+    vt = torch.tensor(v, device="cuda")
+    k = torch.full_like(vt, -1.0)
+    wave_mod.wave_velocity_to_k(vt.data_ptr(), v.size, dt, k.data_ptr(),
+                                torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    ref = ((v.astype(np.float64) * dt) ** 2).astype(np.float32)
+    assert np.array_equal(k.cpu().numpy(), ref)
+    for n, d in ((-1, dt), (10, 0.0), (10, float("nan"))):
+        with pytest.raises(wave_mod.WaveError) as e:
+            wave_mod.wave_velocity_to_k(vt.data_ptr(), n, d, k.data_ptr(), None)
+        assert e.value.code == wave_mod.WAVE_EINVAL
+
+
+def _velocity_gradient(wave, p, v32, tg, every, scales):
+    prop = make_prop(wave, p)
+    prop.forward_checkpointed(p.nt, src_of(p), every)
+    tgt = torch.tensor(tg, dtype=torch.float32, device="cuda")
+    gk = prop.adjoint(tgt).cpu().numpy()
+    gv = prop.adjoint_velocity(tgt, torch.tensor(v32, device="cuda"), p.dt, scales).cpu().numpy()
+    prop.close()
+    return gk, gv
+
+
+def test_adjoint_velocity_chain_rule_and_source_term(wave_mod, oracle_lib, ragged, ragged_tg):
+    # dJ/dv = 2 dt^2 v dJ/dk cell by cell.  With the source values made from
+    # the velocity at the source cell (Eq. 2's dt^2 V^2 f, s_n = k_src w_n /
+    # (dx dy dz)), dJ/dk at that cell gains the derivative through them; it
+    # is pinned by a central difference of the FP64 oracle's J = <g, traces>
+    # in which the source values are remade from the perturbed k.
+    p, tg = ragged, ragged_tg
+    v32 = p.v.astype(np.float32)
+    k32 = p.k32()
+    gk, gv0 = _velocity_gradient(wave_mod, p, v32, tg, 7, False)
+    _, gv1 = _velocity_gradient(wave_mod, p, v32, tg, 7, True)
+    chain = 2.0 * p.dt * p.dt * v32.astype(np.float64)
+    assert np.allclose(gv0, gk * chain, rtol=1e-14, atol=0.0)
+    src = tuple(p.src)
+    other = np.ones(gv0.shape, dtype=bool)
+    other[src] = False
+    assert np.array_equal(gv0[other], gv1[other])  # only the source cell changes
+
+    kk = p.k64()
+    w = p.s / kk[src]  # the wavelet part, fixed
+
+    def J(ksrc):
+        k2 = kk.copy()
+        k2[src] = ksrc
+        _, _, tr = oracle_lib.run(k2, p.h, p.nt, s=ksrc * w, src=p.src, rec=p.rec,
+                                  sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+        return float(np.sum(tg * tr))
+
+    eps = 1e-4 * kk[src]
+    fd = (J(kk[src] + eps) - J(kk[src] - eps)) / (2 * eps)
+    got = gv1[src] / chain[src]
+    fixed = gv0[src] / chain[src]
+    print(f"source cell dJ/dk: {got:.8e} (oracle central difference {fd:.8e}); with the source "
+          f"values fixed {fixed:.8e}")
+    assert abs(got - fd) <= 1e-4 * abs(fd)
+    assert abs(got - fixed) > 1e-2 * abs(fd)  # the source term is not negligible here
+
+
+def test_autograd_with_source_scaling(wave_mod, crop):
+    # traces_of_velocity with source values made from v at the source cell:
+    # the autograd gradient against a central difference of the GPU misfit
+    # along a direction that covers the source cell, the source values
+    # remade from the perturbed v at each evaluation
+    p, q = crop.shot, crop.observed()
+    obs = make_prop(wave_mod, q)
+    obs.run(q.nt, src_of(q))
+    obs.sync()
+    d_obs = obs.traces[:, :obs.nrec].clone()
+    obs.close()
+    w = p.s / (float(p.v[p.src]) * p.dt) ** 2
+
+    def J_of(vv):
+        vs = float(vv.detach()[p.src].double().item())
+        survey = wave_mod.Survey(p.h, p.dt, p.nt, p.src, w * (vs * p.dt) ** 2, p.rec, p.sponge_width,
+                                 p.sponge_alpha, every=crop.every, source_scales_with_v=True)
+        tr = wave_mod.traces_of_velocity(vv, survey)
+        return 0.5 * ((tr.double() - d_obs.double()) ** 2).sum()
+
+    v = torch.tensor(p.v, dtype=torch.float32, device="cuda", requires_grad=True)
+    J = J_of(v)
+    J.backward()
+    gv = v.grad.double()
+    # J is strongly curved at the source (the trace amplitudes scale with
+    # v_src^2), so the central differences at 10 and 5 m/s are combined by
+    # Richardson extrapolation (error O(a^4)); on the oracle the plain
+    # central difference at 20 m/s is 0.8 % off its limit
+    m = p.nx
+    z, y, x = np.ogrid[:m, :m, :m]
+    c = p.src
+    bump = np.exp(-((z - c[0]) ** 2 + (y - c[1]) ** 2 + (x - c[2]) ** 2) / (2 * 3.0 ** 2))
+    d = torch.tensor(bump, dtype=torch.float64, device="cuda")
+    fd = {}
+    with torch.no_grad():
+        for a in (10.0, 5.0):
+            jp = J_of((v.double() + a * d).float()).item()
+            jm = J_of((v.double() - a * d).float()).item()
+            fd[a] = (jp - jm) / (2.0 * a)
+    rich = (4.0 * fd[5.0] - fd[10.0]) / 3.0
+    an = float((gv * d).sum().item())
+    print(f"J {J.item():.6e}; directional derivative at the source: adjoint {an:.6e}, central "
+          f"differences {fd[10.0]:.6e} (10 m/s), {fd[5.0]:.6e} (5 m/s), extrapolated {rich:.6e}")
+    assert abs(an - rich) <= 1e-3 * abs(rich)
