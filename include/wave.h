@@ -190,6 +190,19 @@ int wave_config(const wave_ctx *ctx, int32_t *variant, int32_t *zchunk, int32_t 
  * unstable (for instance a k edited after init) shows up here. */
 int wave_check(wave_ctx *ctx, int64_t *field_nonfinite, int64_t *trace_nonfinite);
 
+/* wave_check for callers that cannot allocate device memory (a loop that
+ * checks the run every few steps, harnesses that forbid hipMalloc): the
+ * same counts, with the two counters held in a fixed device array of the
+ * library (64 ints, 256-byte aligned, one per GPU, kept until the process
+ * ends; its address is looked up by wave_init) instead of a buffer
+ * allocated and freed per call.  Allocates nothing; clears the counters
+ * with a kernel, then synchronises the context's stream as wave_check
+ * does.  Every context on one GPU shares the array: calls that overlap on
+ * one GPU (from several host threads or streams) race and may report each
+ * other's counts.  WAVE_EHIP if the array's address cannot be obtained or
+ * a launch or copy fails. */
+int wave_check_noalloc(wave_ctx *ctx, int64_t *field_nonfinite, int64_t *trace_nonfinite);
+
 /* Wait for all work enqueued on the context's stream; WAVE_EHIP if it or
  * any earlier launch failed. */
 int wave_sync(wave_ctx *ctx);

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -19,6 +20,47 @@
 #include "wave_kernels.h"
 
 using namespace wavek;
+
+// Scratch of wave_check_noalloc: its two counters live in this fixed device
+// array (one copy per GPU, kept until the process ends), so that the call
+// allocates nothing.  On the host `scratch` is only a stand-in for the
+// symbol, not a device address: host code uses the address
+// hipGetSymbolAddress returns for each device (scratch_for), never the name.
+constexpr int kScratchInts = 64;
+static __device__ __align__(256) int scratch[kScratchInts];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+int *scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current (wave_init does it for the context's device).
+int scratch_for(int device, int **out)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return WAVE_EINVAL;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[device]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess)
+            return WAVE_EHIP;
+        if (cur != device && hipSetDevice(device) != hipSuccess)
+            return WAVE_EHIP;
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device)
+            (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return WAVE_EHIP;
+        scratch_dev[device] = static_cast<int *>(p);
+    }
+    *out = scratch_dev[device];
+    return WAVE_OK;
+}
+
+}  // namespace
 
 namespace {
 // ---------------------------------------------------------------------------
@@ -1192,6 +1234,14 @@ int wave_init(wave_ctx **out, const wave_params_t *p, const void *k, void *u_cur
     };
     if (hipGetDevice(&c->device) != hipSuccess)
         return bail(WAVE_EHIP);
+    // the device address of the fixed scratch array, once per device
+    {
+        int *sp = nullptr;
+        if (scratch_for(c->device, &sp) != WAVE_OK) {
+            (void)hipGetLastError();
+            return bail(WAVE_EHIP);
+        }
+    }
 
     // sponge profiles
     std::vector<float> g;
@@ -1778,6 +1828,36 @@ int wave_grad_info(const wave_ctx *ctx, int32_t *nt, int32_t *every, int32_t *se
         *segments = g.nseg;
     if (bytes)
         *bytes = int64_t(g.slab_levels * level_bytes(ctx));
+    return WAVE_OK;
+}
+
+int wave_check_noalloc(wave_ctx *ctx, int64_t *field_nonfinite, int64_t *trace_nonfinite)
+{
+    if (!ctx)
+        return WAVE_EINVAL;
+    constexpr int kCounters = 2;
+    static_assert(kCounters <= kScratchInts, "the counters must fit in the scratch array");
+    int *d = nullptr;
+    if (scratch_for(ctx->device, &d) != WAVE_OK)
+        return fail(ctx, WAVE_EHIP, "wave_check_noalloc: the scratch array's address is not available");
+    int h[kCounters] = {0, 0};
+    const long long cells = (long long)ctx->p.nx * ctx->p.ny * ctx->p.nz;
+    const long long nt = (ctx->traces && ctx->nrec > 0) ? std::min<long long>(ctx->step, ctx->trace_cap) : 0;
+    // the array keeps the last call's counts: clear them with a kernel first
+    hipLaunchKernelGGL(zero_ints, dim3(1), dim3(256), 0, ctx->stream, d, (long long)kCounters);
+    const dim3 g((unsigned)std::min<long long>((std::max(cells, nt * ctx->nrec) + 255) / 256, 4096));
+    hipLaunchKernelGGL(count_nonfinite, g, dim3(256), 0, ctx->stream, (const void *)ctx->cur, ctx->p.dtype,
+                       ctx->p.nx, ctx->p.ny, ctx->p.nz, int(ctx->lay.pitch_x), int(ctx->lay.x_offset),
+                       (long long)ctx->lay.plane, (const float *)ctx->traces, nt * ctx->nrec, d);
+    const bool ok = hipGetLastError() == hipSuccess &&
+                    hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, ctx->stream) == hipSuccess &&
+                    hipStreamSynchronize(ctx->stream) == hipSuccess;
+    if (!ok)
+        return fail(ctx, WAVE_EHIP, "wave_check_noalloc failed");
+    if (field_nonfinite)
+        *field_nonfinite = h[0];
+    if (trace_nonfinite)
+        *trace_nonfinite = h[1];
     return WAVE_OK;
 }
 

@@ -87,6 +87,7 @@ def _load():
         "wave_set_adjoint_fusion": ([vp, i32], ci),
         "wave_set_graph": ([vp, i32], ci),
         "wave_check": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], ci),
+        "wave_check_noalloc": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], ci),
         "wave_grad_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                             ctypes.POINTER(i64)], ci),
         "wave_misfit": ([vp, vp, i64, vp, vp, vp], ci),
@@ -235,6 +236,12 @@ def wave_velocity_to_k(v_ptr, n: int, dt: float, k_ptr, stream):
 def wave_check(ctx):
     f, t = ctypes.c_int64(), ctypes.c_int64()
     _check(_lib.wave_check(ctx, ctypes.byref(f), ctypes.byref(t)), ctx)
+    return f.value, t.value
+
+
+def wave_check_noalloc(ctx):
+    f, t = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.wave_check_noalloc(ctx, ctypes.byref(f), ctypes.byref(t)), ctx)
     return f.value, t.value
 
 
