@@ -325,11 +325,46 @@ def batched_leg(reps: int):
     t_batch = (time.perf_counter() - t0) / reps
     equal = all(torch.equal(a, pr.traces) for a, pr in zip(seq_traces, props))
     b.close()
+
+    # the 32 shots in one launch: every shot with the same kernel (the one
+    # the tuner chose for most cells, or the 128x16 tile), schedule 3
+    names = {}
+    for p_, pr in zip(shots, props):
+        v, zc, _ = pr.config()
+        n = wave.wave_variant_name(v)
+        names[n] = names.get(n, 0) + p_.points
+    common = max(names, key=names.get) if choice["schedule"] != 1 else "t128x16_r1"
+    for pr in props:
+        _, zc, _ = pr.config()
+        pr.configure(common, zc)
+    b1 = wave.Batch(props, stream=stream, use_graph=False)
+    b1.set_schedule(3)
+    one_groups = b1.info()[0]
+
+    def once1():
+        for pr in props:
+            pr.reset()
+        b1.run(nt, srcs)
+
+    once1()
+    b1.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        once1()
+    b1.sync()
+    torch.cuda.synchronize()
+    t_one = (time.perf_counter() - t0) / reps
+    equal1 = all(torch.equal(a, pr.traces) for a, pr in zip(seq_traces, props))
+    b1.close()
+    log(f"batched in one launch ({common}, {one_groups} group): {t_one * 1e3:.1f} ms "
+        f"({32 / t_one:.1f} shots/s, {points * nt / t_one / 1e9:.1f} Gpts/s); traces equal: {equal1}")
     for pr in props:
         pr.close()
     gpts = points * nt / t_batch / 1e9
-    sched = ("one persistent launch per step and kernel group" if choice["schedule"] == 0 else
-             f"every shot with its own tuned kernel on {choice['nstreams']} streams")
+    sched = {0: "one persistent launch per step and kernel group",
+             3: "one launch per kernel group for the whole run (grid barrier between steps)"}.get(
+        choice["schedule"], f"every shot with its own tuned kernel on {choice['nstreams']} streams")
     log(f"batched ({sched}): 32 shots in {t_batch * 1e3:.1f} ms ({32 / t_batch:.1f} shots/s, "
         f"{gpts:.1f} Gpts/s); sequential {t_seq * 1e3:.1f} ms; speedup {t_seq / t_batch:.2f}x; "
         f"traces equal: {equal}; tuning {t_tune:.1f} s")
@@ -340,8 +375,14 @@ def batched_leg(reps: int):
             "speedup_vs_sequential": round(t_seq / t_batch, 3), "graph": True,
             "schedule": choice["schedule"], "schedule_name": sched, "nstreams": choice["nstreams"],
             "tuning_us_per_step": {k: round(v, 1) for k, v in choice["us_per_step"].items()},
-            "launch_groups": groups if choice["schedule"] == 0 else None,
-            "traces_bitwise_equal_to_sequential": bool(equal), "repeats": reps}
+            "launch_groups": groups if choice["schedule"] in (0, 3) else None,
+            "traces_bitwise_equal_to_sequential": bool(equal),
+            "one_launch": {"schedule": 3, "kernel": common, "launch_groups": one_groups,
+                           "ms": round(t_one * 1e3, 2), "shots_per_s": round(32 / t_one, 3),
+                           "gpts_per_s": round(points * nt / t_one / 1e9, 3),
+                           "speedup_vs_sequential": round(t_seq / t_one, 3),
+                           "traces_bitwise_equal_to_sequential": bool(equal1)},
+            "repeats": reps}
 
 
 def gradient_leg(reps: int):
@@ -712,7 +753,8 @@ def main() -> int:
     if not args.no_batched and args.workload == "large_shot":
         prop.close()
         batched = batched_leg(max(1, args.steps // 2))
-        if not batched["traces_bitwise_equal_to_sequential"]:
+        if not (batched["traces_bitwise_equal_to_sequential"]
+                and batched["one_launch"]["traces_bitwise_equal_to_sequential"]):
             log("error: batched traces differ from the sequential runs")
             return 1
 

@@ -345,18 +345,34 @@ int wave_batch_run(wave_batch *b, int32_t nsteps, const float *const *src_dev);
  *               tiles and chunks started as soon as the ones their stencil
  *               reads have finished the step before (per-tile step
  *               counters in place of the launch boundary between steps).
- *               nstreams is ignored.
+ *               nstreams is ignored;
+ *   schedule 3  one cooperative launch per group of shots (shots sharing a
+ *               kernel and storage type) for the whole run: every step is
+ *               schedule 0's work (items taken by ticket from per-XCD
+ *               ranges), and a grid-wide barrier takes the place of the
+ *               launch boundary between steps (agent-scope release on
+ *               arrival, acquire on departure, so no assumption about which
+ *               XCD runs which work-group).  As many work-groups as the GPU
+ *               holds at once.  A barrier wait that runs past a wall-clock
+ *               limit (2 s plus 0.1 ms per step and 0.1 ns per cell update)
+ *               stops the launch and wave_batch_sync returns WAVE_EHIP.  The
+ *               launch is made directly, not captured (use_graph has no
+ *               effect).  nstreams is ignored.  WAVE_EINVAL if the device
+ *               cannot launch cooperative kernels.
  * All give the same results bit for bit as the shots run alone.  Waits for
  * the batch stream; drops a captured graph.  WAVE_EINVAL for another
  * schedule, a stream count out of range, or schedule 1 with graph replay on
  * the legacy default stream, or schedule 2 with shots not stored in FP32;
- * WAVE_EHIP if the library's streams or events cannot be created and
- * WAVE_ENOMEM if the schedule-2 tables cannot be allocated; the batch is
- * then left on schedule 0. */
+ * WAVE_EHIP if the library's streams or events cannot be created or the
+ * schedule-3 launch shape cannot be determined, and WAVE_ENOMEM if the
+ * schedule-2 tables cannot be allocated; the batch is then left on
+ * schedule 0. */
 int wave_batch_set_schedule(wave_batch *b, int32_t schedule, int32_t nstreams);
 
 /* Schedule 2: how many times one dependency wait polls (about 50 ns apart)
- * before it gives up; the default is 2^24.  A wait only ever waits for work
+ * before it gives up; the default is 2^24.  Schedule 3 bounds its barrier
+ * waits by wall-clock time instead and reads only the sign: a negative value
+ * makes every barrier wait give up at once (the same test hook).  A wait only ever waits for work
  * already running, so it ends; the limit is a safety net.  A wait that gives
  * up stops the whole launch, and wave_batch_sync then returns WAVE_EHIP.  A
  * negative value makes every wait after a launch's first step give up (a
@@ -369,7 +385,7 @@ int wave_batch_info(const wave_batch *b, int32_t *groups, int64_t *workgroups_pe
                     int64_t *points_per_step);
 
 /* Wait for the batch stream; WAVE_EHIP if a batched launch failed or, with
- * schedule 2, a dependency wait gave up. */
+ * schedule 2 or 3, a dependency or barrier wait gave up. */
 int wave_batch_sync(wave_batch *b);
 
 int wave_batch_destroy(wave_batch *b);

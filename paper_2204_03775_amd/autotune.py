@@ -3,16 +3,18 @@
 Single shots: every (variant, z-chunk) candidate is timed on the shot's
 own grid (``tune_single``).
 
-Batches (``tune_batch``) can run in two ways.  Schedule 0 puts all shots
-into one persistent launch per step and kernel group; there shots are
-grouped into size classes by the x extent of their grid (the axis tiles
-are widest along, so it decides how many lanes of the last tile idle), and
-every class gets a kernel variant and a z-chunk fraction, timed on the
-batch itself one class at a time (coordinate descent from a common
-start), because a configuration that is best for a shot alone is not best
-when all shots share each launch.  Schedule 1 launches every shot with its
-own tuned configuration, spread over a few streams and replayed from one
-graph.  The faster of the two is kept.
+Batches (``tune_batch``) can run in three ways.  Schedule 0 puts all shots
+into one persistent launch per step and kernel group, and schedule 3 runs
+the same work in one launch per group for the whole run (a grid barrier
+between steps); there shots are grouped into size classes by the x extent
+of their grid (the axis tiles are widest along, so it decides how many
+lanes of the last tile idle), and every class gets a kernel variant and a
+z-chunk fraction, timed on the batch itself one class at a time
+(coordinate descent from a common start), because a configuration that is
+best for a shot alone is not best when all shots share each launch.
+Schedule 1 launches every shot with its own tuned configuration, spread
+over a few streams and replayed from one graph per stream.  The fastest is
+kept.
 
 Results are cached in a JSON file keyed by (GPU architecture, storage type,
 class); ``WAVE_TUNE_CACHE`` overrides its location.
@@ -104,7 +106,8 @@ def _timed_steps(props, srcs, wanted: int, before: int = 0) -> int:
 def time_batch(props, srcs, nsteps: int, stream, schedule: int = 0, nstreams: int = 1) -> float:
     """Seconds per step of one batched run, after a short warm-up; fields
     are reset before and after.  Schedule 0 launches eagerly (one launch per
-    step and group); schedule 1 is captured once and the replay is timed."""
+    step and group); schedule 1 is captured once and the replay is timed;
+    schedule 3 is one launch per group for the whole run."""
     nsteps = _timed_steps(props, srcs, nsteps)
     b = wave.Batch(props, stream=stream, use_graph=(schedule == 1))
     try:
@@ -180,26 +183,28 @@ def tune_single(prop, src, stream, nsteps: int = 20, use_cache: bool = True, log
 
 def tune_batch(props, srcs, stream, nsteps: int = 30, use_cache: bool = True, log=None) -> dict:
     """Choose how to run this batch: schedule 0 (one persistent launch per
-    step and group) with a (variant, chunks) per size class, or schedule 1
-    (every shot with its own tuned configuration on 1, 2 or 4 streams),
-    whichever is faster.  Configures the Propagators and returns
+    step and group) or schedule 3 (one launch per group for the whole run)
+    with a (variant, chunks) per size class, or schedule 1 (every shot with
+    its own tuned configuration on 1, 2 or 4 streams), whichever is fastest.  Configures the Propagators and returns
     {"schedule", "nstreams", "classes" or "shots", "us_per_step"}; create
     the Batch afterwards and call its set_schedule(schedule, nstreams)."""
     classes = tune_classes(props, srcs, stream, nsteps, use_cache, log)
     t_queue = time_batch(props, srcs, nsteps, stream)
+    t_run = time_batch(props, srcs, nsteps, stream, schedule=3)
     shots = [tune_single(p, s, stream, use_cache=use_cache, log=log) for p, s in zip(props, srcs)]
     t_streams = {k: time_batch(props, srcs, nsteps, stream, schedule=1, nstreams=k) for k in STREAM_COUNTS}
     k_best = min(t_streams, key=t_streams.get)
     if log:
-        log(f"tune batch: schedule 0 {t_queue * 1e6:.1f} us/step; schedule 1 "
+        log(f"tune batch: schedule 0 {t_queue * 1e6:.1f} us/step; schedule 3 {t_run * 1e6:.1f}; schedule 1 "
             + ", ".join(f"{k} streams {t * 1e6:.1f}" for k, t in t_streams.items()) + " us/step")
-    times = {"schedule0": t_queue * 1e6, **{f"schedule1_streams{k}": t * 1e6 for k, t in t_streams.items()}}
-    if t_streams[k_best] < t_queue:
+    times = {"schedule0": t_queue * 1e6, "schedule3": t_run * 1e6,
+             **{f"schedule1_streams{k}": t * 1e6 for k, t in t_streams.items()}}
+    if t_streams[k_best] < min(t_queue, t_run):
         return {"schedule": 1, "nstreams": k_best, "shots": [list(x) for x in shots],
                 "us_per_step": times}
     apply(props, classes)
-    return {"schedule": 0, "nstreams": 1, "classes": {k: list(v) for k, v in classes.items()},
-            "us_per_step": times}
+    return {"schedule": 3 if t_run < t_queue else 0, "nstreams": 1,
+            "classes": {k: list(v) for k, v in classes.items()}, "us_per_step": times}
 
 
 def tune_classes(props, srcs, stream, nsteps: int = 30, use_cache: bool = True, log=None) -> dict:

@@ -5,7 +5,8 @@
 namespace wavek {
 
 #define INST(TXV, TY, RY) \
-    template __global__ void step_batch<WAVE_BF16, TXV, TY, RY>(const ShotDesc *__restrict__, BatchItems, int);
+    template __global__ void step_batch<WAVE_BF16, TXV, TY, RY>(const ShotDesc *__restrict__, BatchItems, int); \
+    template __global__ void step_batch_run<WAVE_BF16, TXV, TY, RY>(const ShotDesc *__restrict__, BatchItems, RunSync);
 WAVE_TILE_SHAPES(INST)
 #undef INST
 

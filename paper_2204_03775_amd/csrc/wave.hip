@@ -69,11 +69,13 @@ namespace {
 typedef void (*StepKernel)(StepArgs);
 typedef void (*BatchKernel)(const ShotDesc *, BatchItems, int);
 typedef void (*FlowKernel)(const ShotDesc *, FlowPlan);
+typedef void (*RunKernel)(const ShotDesc *, BatchItems, RunSync);
 
 struct Variant {
     const char *name;
     StepKernel fn[kNumKinds];  // by storage type; all NULL for "auto" and "naive"
     BatchKernel batch[3];      // FP32, FP16, BF16 (two-level storage)
+    RunKernel run[3];          // the same, every step of a run in one launch
     StepKernel adj[3];  // adjoint step, imaging step, fused adjoint + imaging (FP32)
     FlowKernel flow;    // data-flow batched step (FP32)
     int txv, ty, ry;
@@ -85,12 +87,16 @@ struct Variant {
      step_tiled<WAVE_BF16_UV, TXV, TY, RY>},                                                      \
     {step_batch<WAVE_F32, TXV, TY, RY>, step_batch<WAVE_F16, TXV, TY, RY>,                        \
      step_batch<WAVE_BF16, TXV, TY, RY>},                                                         \
+    {step_batch_run<WAVE_F32, TXV, TY, RY>, step_batch_run<WAVE_F16, TXV, TY, RY>,                \
+     step_batch_run<WAVE_BF16, TXV, TY, RY>},                                                     \
     {adjoint_tiled<kAdj, TXV, TY, RY>, adjoint_tiled<kImg, TXV, TY, RY>, adjoint_tiled<kFus, TXV, TY, RY>}, \
     step_flow<TXV, TY, RY>
 
 const Variant kVariants[] = {
-    {"auto", {nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, nullptr, 0, 0, 0},
-    {"naive", {nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, nullptr, 0, 0, 0},
+    {"auto", {nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr},
+     {nullptr, nullptr, nullptr}, nullptr, 0, 0, 0},
+    {"naive", {nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr},
+     {nullptr, nullptr, nullptr}, nullptr, 0, 0, 0},
     {"t64x16_r1", TILED(16, 16, 1), 16, 16, 1},
     {"t128x8_r1", TILED(32, 8, 1), 32, 8, 1},
     {"t128x16_r2", TILED(32, 8, 2), 32, 8, 2},
@@ -772,13 +778,16 @@ int auto_segment(const wave_ctx *c, int nt)
 
 }  // namespace
 
+// schedule 3's barrier words after a group's tickets: count, gen, abort, spare
+constexpr int kRunSyncInts = 4;
+
 struct wave_batch {
     struct Group {
         int kind = 0, variant = 0;
         std::vector<int> shots;       // indices into ctx
         std::vector<ShotDesc> h_desc; // last uploaded descriptors
         ShotDesc *d_desc = nullptr;
-        int *d_items = nullptr;       // shot[items], lid[items], xcd_start[9], counters[16]
+        int *d_items = nullptr;       // shot[items], lid[items], xcd_start[9], counters[16], run sync[4]
         BatchItems items{};
         int total = 0, grid = 0, threads = 0;
         // schedule 2: FlowShot table, xcd_shot[9], xcd_items[8], then the
@@ -788,6 +797,8 @@ struct wave_batch {
         int *flow_counters = nullptr;
         long long flow_ncounters = 0;
         int flow_grid = 0, flow_max_items = 0;
+        // schedule 3: work-groups of the single-launch run (all resident)
+        int run_grid = 0;
     };
     std::vector<wave_ctx *> ctx;
     std::vector<int> cfg;  // (variant, zchunk, nwg) of every shot at creation
@@ -984,6 +995,67 @@ int flow_enqueue(wave_batch *b, int nsteps)
             hipLaunchKernelGGL(kVariants[g.variant].flow, dim3(g.flow_grid), dim3(g.threads), 0, b->stream,
                                (const ShotDesc *)g.d_desc, p);
         }
+    }
+    return hipGetLastError() == hipSuccess ? WAVE_OK : WAVE_EHIP;
+}
+
+// Schedule 3 plans: per group, as many work-groups as the GPU holds at once
+// (the single-launch run waits at grid barriers, so all must be resident),
+// a multiple of 8 so that every XCD's item range has its own work-groups.
+int build_run(wave_batch *b)
+{
+    int device = 0, cus = 0, coop = 0;
+    if (hipGetDevice(&device) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1 ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess)
+        return WAVE_EHIP;
+    if (!coop)
+        return WAVE_EINVAL;
+    for (auto &g : b->groups) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kVariants[g.variant].run[g.kind], g.threads, 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            return WAVE_EHIP;
+        g.run_grid = int((long long)per_cu * cus / 8 * 8);
+        if (g.run_grid < 8)
+            return WAVE_EHIP;
+    }
+    return WAVE_OK;
+}
+
+// Schedule 3: per group, one cooperative launch for all nsteps steps, after
+// clearing its tickets and barrier words.  Every barrier wait of the launch
+// gives up (and flags the run as failed) past a wall-clock limit of 2 s plus
+// 0.1 ms per step and 0.1 ns per cell-update (10 Gpts/s, far below the
+// kernels' rates).
+int run_enqueue(wave_batch *b, int nsteps)
+{
+    int device = 0, khz = 0;
+    if (hipGetDevice(&device) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || khz < 1)
+        return WAVE_EHIP;
+    for (auto &g : b->groups) {
+        long long cells = 0;
+        for (int t : g.shots)
+            cells += (long long)b->ctx[t]->p.nx * b->ctx[t]->p.ny * b->ctx[t]->p.nz;
+        const double seconds = 2.0 + nsteps * (1e-4 + double(cells) * 1e-10);
+        int *words = g.items.counters;
+        hipLaunchKernelGGL(zero_ints, dim3(1), dim3(256), 0, b->stream, words, (long long)(16 + kRunSyncInts));
+        RunSync rs;
+        rs.count = reinterpret_cast<unsigned *>(words + 16);
+        rs.gen = reinterpret_cast<unsigned *>(words + 17);
+        rs.abort = words + 18;
+        // a negative wait limit (a test hook) makes every barrier wait give up at once
+        rs.timeout = b->wait_limit < 0 ? 0ull : (unsigned long long)(seconds * khz * 1000.0);
+        rs.j0 = 0;
+        rs.nsteps = nsteps;
+        const ShotDesc *desc = g.d_desc;
+        BatchItems items = g.items;
+        void *args[] = {&desc, &items, &rs};
+        if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kVariants[g.variant].run[g.kind]),
+                                       dim3(g.run_grid), dim3(g.threads), args, 0, b->stream) != hipSuccess)
+            return WAVE_EHIP;
     }
     return hipGetLastError() == hipSuccess ? WAVE_OK : WAVE_EHIP;
 }
@@ -1977,7 +2049,7 @@ int wave_batch_create(wave_batch **out, wave_ctx *const *ctxs, int32_t nshots, v
         blob.insert(blob.end(), ishot.begin(), ishot.end());
         blob.insert(blob.end(), ilid.begin(), ilid.end());
         blob.insert(blob.end(), xs.begin(), xs.end());
-        blob.insert(blob.end(), 16, 0);
+        blob.insert(blob.end(), 16 + kRunSyncInts, 0);  // tickets [2][8], then the run's barrier words
         g.h_desc.assign(g.shots.size(), ShotDesc{});
         std::memset(g.h_desc.data(), 0, sizeof(ShotDesc) * g.h_desc.size());
         if (hipMalloc(&g.d_desc, sizeof(ShotDesc) * g.shots.size()) != hipSuccess ||
@@ -2097,7 +2169,11 @@ int wave_batch_run(wave_batch *b, int32_t nsteps, const float *const *src_dev)
             g.h_desc = d;
         }
     }
-    if (nsteps > 0) {
+    if (nsteps > 0 && b->schedule == 3) {
+        // one launch per group for the whole run: nothing to capture
+        if (run_enqueue(b, nsteps) != WAVE_OK)
+            return bfail(b, WAVE_EHIP, "single-launch run failed to start");
+    } else if (nsteps > 0) {
         if (b->use_graph) {
             if (b->graph_steps != nsteps) {
                 // a replaced graph may still be running: wait before destroying it
@@ -2149,8 +2225,8 @@ int wave_batch_set_schedule(wave_batch *b, int32_t schedule, int32_t nstreams)
 {
     if (!b)
         return WAVE_EINVAL;
-    if (schedule < 0 || schedule > 2 || (schedule == 1 && (nstreams < 1 || nstreams > 16)))
-        return bfail(b, WAVE_EINVAL, "schedule must be 0, 1 with 1..16 streams, or 2");
+    if (schedule < 0 || schedule > 3 || (schedule == 1 && (nstreams < 1 || nstreams > 16)))
+        return bfail(b, WAVE_EINVAL, "schedule must be 0, 1 with 1..16 streams, 2 or 3");
     if (schedule == 2 && !kFlowScheduleEnabled)
         return bfail(b, WAVE_EINVAL,
                      "schedule 2 is switched off: its first GPU run did not complete and the cause is not known");
@@ -2173,6 +2249,13 @@ int wave_batch_set_schedule(wave_batch *b, int32_t schedule, int32_t nstreams)
             return bfail(b, rc, "schedule 2 plan could not be built");
         }
         b->schedule = 2;
+    }
+    if (schedule == 3) {
+        const int rc = build_run(b);
+        if (rc != WAVE_OK)
+            return bfail(b, rc, rc == WAVE_EINVAL ? "schedule 3 needs cooperative launches, which the device lacks"
+                                                  : "schedule 3 plan could not be built");
+        b->schedule = 3;
     }
     if (schedule == 1) {
         // on any failure the batch stays on schedule 0 with no streams
@@ -2224,6 +2307,14 @@ int wave_batch_sync(wave_batch *b)
                 return bfail(b, WAVE_EHIP, "schedule 2 status could not be read");
             if (flag)
                 return bfail(b, WAVE_EHIP, "schedule 2: a dependency wait gave up; the run's results are invalid");
+        }
+    if (b->schedule == 3)
+        for (const auto &g : b->groups) {
+            int flag = 0;
+            if (hipMemcpy(&flag, g.items.counters + 18, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+                return bfail(b, WAVE_EHIP, "schedule 3 status could not be read");
+            if (flag)
+                return bfail(b, WAVE_EHIP, "schedule 3: a barrier wait ran past its limit; the run's results are invalid");
         }
     return WAVE_OK;
 }

@@ -108,6 +108,17 @@ struct BatchItems {
     int *counters;         // [2][8] tickets of the current and the next step
 };
 
+// Single-launch run of a batch (schedule 3): the grid barrier between steps
+// and its bound.  count, gen and abort are zero at launch.
+struct RunSync {
+    unsigned *count;             // work-groups arrived at the current barrier
+    unsigned *gen;               // barriers opened so far
+    int *abort;                  // raised when a barrier wait runs past the limit
+    unsigned long long timeout;  // wall-clock ticks a work-group may wait in all
+    int j0;                      // step of the run at which this launch starts
+    int nsteps;                  // steps of this launch
+};
+
 // Data-flow schedule: one launch runs every step of a group of shots.  Each
 // shot is pinned to one XCD; an item is (step, shot, tile, z-chunk).
 struct FlowShot {

@@ -15,6 +15,9 @@ __global__ __launch_bounds__(TXV *TY) void adjoint_tiled(StepArgs a);
 template <int KIND, int TXV, int TY, int RY>
 __global__ __launch_bounds__(TXV *TY) void step_batch(const ShotDesc *__restrict__ shots, BatchItems it,
                                                        int j);
+template <int KIND, int TXV, int TY, int RY>
+__global__ __launch_bounds__(TXV *TY) void step_batch_run(const ShotDesc *__restrict__ shots, BatchItems it,
+                                                           RunSync rs);
 template <int TXV, int TY, int RY>
 __global__ __launch_bounds__(TXV *TY) void step_flow(const ShotDesc *__restrict__ shots, FlowPlan p);
 template <int KIND>

@@ -150,23 +150,40 @@ constexpr int kStream = 2;
 // reached the L2 before they signal completion)
 constexpr int kCoh = 16;
 
-// Four consecutive cells, decoded to FP32 (times `scale` for 16-bit data).
+// Four consecutive cells as stored (16 bytes of FP32, 8 bytes of 16-bit
+// values), and decoded to FP32 (times `scale` for 16-bit data).  Values
+// loaded ahead of their use are held raw, so that a 16-bit prefetch holds
+// half the registers of its decoded form.
+template <int KIND>
+using Raw4 = std::conditional_t<KIND == WAVE_F32, u4raw, u2raw>;
+
 template <int KIND, int POL>
-__device__ __forceinline__ f4 load4(__amdgpu_buffer_rsrc_t r, unsigned off, float scale)
+__device__ __forceinline__ Raw4<KIND> load_raw4(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    if constexpr (KIND == WAVE_F32)
+        return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, POL);
+    else
+        return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, POL);
+}
+
+template <int KIND>
+__device__ __forceinline__ f4 decode4(const Raw4<KIND> &v, float scale = 1.f)
 {
     f4 o;
-    if constexpr (KIND == WAVE_F32) {
-        const u4raw v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, POL);
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+    for (int e = 0; e < 4; ++e) {
+        if constexpr (KIND == WAVE_F32)
             o.v[e] = __uint_as_float(v[e]);
-    } else {
-        const u2raw v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, POL);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
+        else
             o.v[e] = Store<KIND>::dec((v[e >> 1] >> (16 * (e & 1))) & 0xffffu) * scale;
     }
     return o;
+}
+
+template <int KIND, int POL>
+__device__ __forceinline__ f4 load4(__amdgpu_buffer_rsrc_t r, unsigned off, float scale)
+{
+    return decode4<KIND>(load_raw4<KIND, POL>(r, off), scale);
 }
 
 template <int KIND>
@@ -509,7 +526,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
 
     // values of the next plane, loaded one plane ahead into the set of the
     // other parity (no copies, so no wait before the next loads are issued)
-    f4 pv[2][RY], kv[2][RY], hv[2][HPT];
+    Raw4<KIND> pv[2][RY], kv[2][RY], hv[2][HPT];
     f4 hv2[FUS ? 2 : 1][FUS ? HPT : 1];
     float gzv[2], gzq[2];  // g_z of the plane and (adjoint) of the queue plane z + 4
     auto prefetch = [&](int z, int slot, int set) {
@@ -520,12 +537,12 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             q[slot][r] = load4<KIND, PK>(rq, own_ld[r], 1.f);
-            pv[set][r] = load4<KIND, PS>(rp, own_in[r], 1.f);
-            kv[set][r] = load4<KIND, kStream>(rk, own_in[r], 1.f);
+            pv[set][r] = load_raw4<KIND, PS>(rp, own_in[r]);
+            kv[set][r] = load_raw4<KIND, kStream>(rk, own_in[r]);
         }
 #pragma unroll
         for (int h = 0; h < HPT; ++h)
-            hv[set][h] = load4<KIND, PK>(rh, h_b[h], 1.f);
+            hv[set][h] = load_raw4<KIND, PK>(rh, h_b[h]);
         if constexpr (FUS) {
             const __amdgpu_buffer_rsrc_t raq = stencil_plane_rsrc(a.aux, pbytes, z + 4, a.nz);
             const __amdgpu_buffer_rsrc_t rah = plane_rsrc(a.aux, pbytes, z);
@@ -576,11 +593,6 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
                         q[(s + 8) % QS][r].v[e] *= gown[r].v[e] * gzq[cur_set];
-#pragma unroll
-                for (int h = 0; h < HPT; ++h)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        hv[cur_set][h].v[e] *= gh[h].v[e] * gzv[cur_set];
             }
             const int b = z & 1;
             f4 *L = &lds[b][0][0];
@@ -588,9 +600,16 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
             for (int r = 0; r < RY; ++r)
                 L[(4 + ly * RY + r) * LW + lx + 1] = q[(s + 4) % QS][r];
 #pragma unroll
-            for (int h = 0; h < HPT; ++h)
+            for (int h = 0; h < HPT; ++h) {
+                f4 hd = decode4<KIND>(hv[cur_set][h]);
+                if constexpr (ADJ) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        hd.v[e] *= gh[h].v[e] * gzv[cur_set];
+                }
                 if (h_lds[h] >= 0)
-                    L[h_lds[h]] = hv[cur_set][h];
+                    L[h_lds[h]] = hd;
+            }
             f4 *L2 = &lds2[FUS ? b : 0][0][0];
             if constexpr (FUS) {
 #pragma unroll
@@ -628,6 +647,8 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
             const __amdgpu_buffer_rsrc_t rdl = plane_rsrc(UV ? a.dlt : a.out, pbytes, z);
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
+                const f4 pvd = decode4<KIND>(pv[cur_set][r]);
+                const f4 kvd = decode4<KIND>(kv[cur_set][r]);
                 const f4 xl = L[(4 + ly * RY + r) * LW + lx];
                 const f4 xr = L[(4 + ly * RY + r) * LW + lx + 2];
                 const f4 ctr = q[(s + 4) % QS][r];
@@ -681,10 +702,10 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
                     const float g = gxv.v[e] * gyv[r] * gzv[cur_set];
                     if constexpr (IMG) {
                         // imaging term (G phi / k) lap a
-                        out.v[e] = (g * pv[cur_set][r].v[e]) / kv[cur_set][r].v[e] * lap;
+                        out.v[e] = (g * pvd.v[e]) / kvd.v[e] * lap;
                     } else if constexpr (ADJ) {
-                        const float t = fmaf(kv[cur_set][r].v[e], lap, 2.f * ctr.v[e]);
-                        out.v[e] = fmaf(-g * g, pv[cur_set][r].v[e], t);
+                        const float t = fmaf(kvd.v[e], lap, 2.f * ctr.v[e]);
+                        out.v[e] = fmaf(-g * g, pvd.v[e], t);
                         if constexpr (FUS) {
                             // imaging term of the step after this one: the
                             // centre already holds G phi, bit for bit g * phi
@@ -700,19 +721,19 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
                                                 u2b,
                                             lap2);
                             }
-                            img.v[e] = ctr.v[e] / kv[cur_set][r].v[e] * lap2;
+                            img.v[e] = ctr.v[e] / kvd.v[e] * lap2;
                         }
                     } else {
                         float t, pe;
                         if constexpr (SCALED) {
-                            t = fmaf(kv[cur_set][r].v[e], lap, fd.two_a * ctr.v[e]);
+                            t = fmaf(kvd.v[e], lap, fd.two_a * ctr.v[e]);
                             if constexpr (UV)  // u^{n-1} = u^n - d^n
-                                pe = fmaf(-fd.b, pv[cur_set][r].v[e], fd.a * ctr.v[e]);
+                                pe = fmaf(-fd.b, pvd.v[e], fd.a * ctr.v[e]);
                             else
-                                pe = fd.b * pv[cur_set][r].v[e];
+                                pe = fd.b * pvd.v[e];
                         } else {
-                            t = fmaf(kv[cur_set][r].v[e], lap, 2.f * ctr.v[e]);
-                            pe = pv[cur_set][r].v[e];
+                            t = fmaf(kvd.v[e], lap, 2.f * ctr.v[e]);
+                            pe = pvd.v[e];
                         }
                         t = fmaf(-g, pe, t);
                         out.v[e] = g * t;
@@ -816,18 +837,17 @@ __global__ __launch_bounds__(TXV *TY) void adjoint_tiled(StepArgs a)
 // many shots per launch
 
 
-// One time step of every shot in a group, as a persistent launch: the grid
-// holds as many work-groups as fit on the GPU at once; work-group b runs on
-// XCD b % 8 (blocks are dealt to the XCDs round-robin) and takes items of
-// that XCD's range by atomic ticket until the range is exhausted, so long
-// and short items balance dynamically while neighbouring tiles still share
-// an XCD's L2.  Step j draws from counter set j & 1 and clears set
-// (j + 1) & 1 for the next step (which starts only after this one ends).
+// The items of one time step j of every shot in a group: work-group b runs
+// on XCD b % 8 (blocks are dealt to the XCDs round-robin) and takes items
+// of that XCD's range by atomic ticket until the range is exhausted, so
+// long and short items balance dynamically while neighbouring tiles still
+// share an XCD's L2.  Step j draws from counter set j & 1 and clears set
+// (j + 1) & 1 for the next step, which starts only after this one has ended
+// (a launch boundary, or a grid barrier in the single-launch run).
 template <int KIND, int TXV, int TY, int RY>
-__global__ __launch_bounds__(TXV *TY) void step_batch(const ShotDesc *__restrict__ shots,
-                                                       BatchItems it, int j)
+__device__ __forceinline__ void batch_step_items(const ShotDesc *__restrict__ shots, const BatchItems &it, int j,
+                                                 int &ticket)
 {
-    __shared__ int ticket;
     const int xcd = blockIdx.x & 7;
     int *cnt = it.counters + 8 * (j & 1);
     if (blockIdx.x == 0 && threadIdx.x < 8)
@@ -860,7 +880,67 @@ __global__ __launch_bounds__(TXV *TY) void step_batch(const ShotDesc *__restrict
     }
 }
 
+// One time step of every shot in a group as a persistent launch: the grid
+// holds as many work-groups as fit on the GPU at once.
+template <int KIND, int TXV, int TY, int RY>
+__global__ __launch_bounds__(TXV *TY) void step_batch(const ShotDesc *__restrict__ shots,
+                                                       BatchItems it, int j)
+{
+    __shared__ int ticket;
+    batch_step_items<KIND, TXV, TY, RY>(shots, it, j, ticket);
+}
 
+// Every step of a run of every shot in a group in one cooperative launch
+// (all work-groups resident at once).  Each step is the work of step_batch;
+// a grid-wide barrier replaces the launch boundary between steps.  Before
+// a work-group arrives, its stores are made visible device-wide: every
+// thread waits for its own stores to complete, then thread 0 arrives with an
+// agent-scope release (which writes back its XCD's L2).  It leaves after an
+// agent-scope acquire, so a step reads what the step before wrote on any
+// XCD.  Every wait is bounded by a wall-clock limit and a shared abort flag:
+// a wait that runs past the limit raises the flag, every work-group stops
+// at its next barrier, and the host reports the run as failed.
+template <int KIND, int TXV, int TY, int RY>
+__global__ __launch_bounds__(TXV *TY) void step_batch_run(const ShotDesc *__restrict__ shots, BatchItems it,
+                                                           RunSync rs)
+{
+    __shared__ int ticket;
+    __shared__ int stop;
+    const unsigned long long deadline = wall_clock64() + rs.timeout;
+    unsigned gen = 0;  // barriers this work-group has passed
+    for (int jj = 0; jj < rs.nsteps; ++jj) {
+        batch_step_items<KIND, TXV, TY, RY>(shots, it, rs.j0 + jj, ticket);
+        if (jj + 1 == rs.nsteps)
+            break;  // the launch boundary orders the last step
+        __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            stop = 0;
+            const unsigned arrived =
+                __hip_atomic_fetch_add(rs.count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (arrived + 1 == gridDim.x) {
+                // the last to arrive opens the barrier for everyone
+                __hip_atomic_store(rs.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(rs.gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                while (__hip_atomic_load(rs.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                    if (wall_clock64() > deadline ||
+                        __hip_atomic_load(rs.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        __hip_atomic_store(rs.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        stop = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            ++gen;
+        }
+        __syncthreads();
+        if (stop)
+            return;
+    }
+}
 
 // Schedule 2 (switched off in the host code; see there): every step of
 // every shot of a group in one launch (FP32).

@@ -544,9 +544,9 @@ class Batch:
 
     def set_schedule(self, schedule: int, nstreams: int = 1):
         """0: one persistent launch per step and kernel group; 1: every
-        shot with its own kernel on ``nstreams`` streams; 2 (FP32): one
-        launch per kernel group for the whole run, each shot on one XCD,
-        tiles started as their neighbours finish the previous step."""
+        shot with its own kernel on ``nstreams`` streams; 2: switched off
+        (the library refuses it); 3: one cooperative launch per kernel
+        group for the whole run, a grid barrier between steps."""
         wave_batch_set_schedule(self.handle, schedule, nstreams)
         self.schedule, self.nstreams = int(schedule), int(nstreams)
 

@@ -1,7 +1,9 @@
 """Batched multi-shot runs: one persistent launch per step for many shots
 (schedule 0), every shot with its own kernel over several streams
-(schedule 1), or one launch for the whole run with shots pinned to XCDs and
-per-tile step counters (schedule 2), optionally replayed from a HIP graph.
+(schedule 1), one launch for the whole run with shots pinned to XCDs and
+per-tile step counters (schedule 2, switched off), or one cooperative
+launch for the whole run with a grid barrier between steps (schedule 3),
+optionally replayed from a HIP graph.
 
 Exact: every shot of a batch reproduces, bit for bit, the same shot run
 alone with the same kernel configuration -- fields, buffer roles and
@@ -222,7 +224,7 @@ def test_autotune_choice_is_applied(wave_mod, tmp_path, monkeypatch):
     assert autotune.tune_single(props[0], srcs[0], stream) == one
     # the whole batch: a schedule, and the shots configured for it
     choice = autotune.tune_batch(props, srcs, stream, nsteps=5)
-    assert choice["schedule"] in (0, 1) and choice["nstreams"] >= 1
+    assert choice["schedule"] in (0, 1, 3) and choice["nstreams"] >= 1
     if choice["schedule"] == 1:
         for pr, (name, zc) in zip(props, choice["shots"]):
             v, zc_used, _ = pr.config()
@@ -266,19 +268,92 @@ def test_per_shot_schedule_matches_individual_runs(wave_mod, nstreams, graph):
         pr.close()
 
 
+# schedule 3: one cooperative launch per kernel group for the whole run,
+# a grid barrier between steps
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_single_launch_schedule_matches_individual_runs(wave_mod, dtype):
+    shots = make_shots()
+    ref = alone(wave_mod, shots, dtype)
+    props, srcs = build(wave_mod, shots, dtype)
+    b = wave_mod.Batch(props, use_graph=True)
+    b.set_schedule(3)
+    nt = shots[0].nt
+    junk = torch.randn(1 << 20, device="cuda")
+    for rep, split in enumerate((True, False, False)):
+        print(f"case: schedule 3, {dtype}, run {rep}, split={split}", flush=True)
+        for pr in props:
+            pr.reset()
+        if split:  # an odd and an even part (role bookkeeping across launches)
+            b.run(9, srcs)
+            b.run(nt - 9, [s[9:] for s in srcs])
+        else:
+            b.run(nt, srcs)
+        junk.mul_(1.0001)
+        b.sync()
+        torch.cuda.synchronize()
+        for i, pr in enumerate(props):
+            assert same(snapshot(pr), ref[i]), (rep, i)
+    b.close()
+    for pr in props:
+        pr.close()
+
+
+def test_single_launch_schedule_one_group_and_failure_path(wave_mod):
+    # every shot with the same kernel: the whole run of all shots is one
+    # launch; then the failure hook (every barrier wait gives up at once)
+    # stops it early, the kernel exits normally and the run is reported
+    # failed; a normal run afterwards is exact again
+    shots = make_shots()
+    cfgs = [("t128x16_r1", zc) for zc in (0, 16, 7, 0, 24, 56)]
+    props, srcs = build(wave_mod, shots, "f32", cfgs)
+    ref = []
+    for pr, s, p in zip(props, srcs, shots):
+        pr.run(p.nt, s)
+        pr.sync()
+        ref.append(snapshot(pr))
+        pr.reset()
+    b = wave_mod.Batch(props, use_graph=False)
+    assert b.info()[0] == 1
+    b.set_schedule(3)
+    print("case: schedule 3, one group", flush=True)
+    b.run(shots[0].nt, srcs)
+    b.sync()
+    for i, pr in enumerate(props):
+        assert same(snapshot(pr), ref[i]), i
+    for pr in props:
+        pr.reset()
+    b.set_wait_limit(-1)
+    print("case: schedule 3, failure path", flush=True)
+    b.run(shots[0].nt, srcs)
+    with pytest.raises(wave_mod.WaveError) as e:
+        b.sync()
+    assert e.value.code == wave_mod.WAVE_EHIP
+    b.set_wait_limit(1 << 24)
+    for pr in props:
+        pr.reset()
+    print("case: schedule 3, after the failure path", flush=True)
+    b.run(shots[0].nt, srcs)
+    b.sync()
+    for i, pr in enumerate(props):
+        assert same(snapshot(pr), ref[i]), i
+    b.close()
+    for pr in props:
+        pr.close()
+
+
 def test_schedule_switch_and_bad_arguments(wave_mod):
     shots = make_shots()
     ref = alone(wave_mod, shots, "f32")
     props, srcs = build(wave_mod, shots, "f32")
     b = wave_mod.Batch(props, use_graph=True)
     # schedule 2 is switched off and rejected
-    for sched, ns in ((1, 0), (1, 17), (3, 1), (-1, 1), (2, 1)):
+    for sched, ns in ((1, 0), (1, 17), (4, 1), (-1, 1), (2, 1)):
         with pytest.raises(wave_mod.WaveError) as e:
             wave_mod.wave_batch_set_schedule(b.handle, sched, ns)
         assert e.value.code == wave_mod.WAVE_EINVAL
     nt = shots[0].nt
     # every switch drops the captured graph; each run is checked in full
-    for sched, ns in ((1, 2), (0, 1), (1, 4), (1, 4)):
+    for sched, ns in ((1, 2), (0, 1), (3, 1), (1, 4), (3, 1), (1, 4)):
         print(f"case: schedule {sched}, {ns} streams, graph", flush=True)
         b.set_schedule(sched, ns)
         for pr in props:
