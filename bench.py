@@ -38,7 +38,9 @@ HBM before timing starts.  The JSON line on stdout carries:
              another with the library's automatic configuration (their
              traces must agree bit for bit).
   launch     the 64^3 x 100-step parity shot (launch-bound): eager launches
-             against graph replay of the whole run;
+             against graph replay of the whole run, and what one step costs
+             if the work-groups of a single launch synchronise between steps
+             instead (grid barrier, neighbour flags; a probe kernel);
   gradient   the least-squares misfit gradient with respect to k on a 256^3
              layered model with a Gaussian anomaly (800 steps, 128
              receivers): checkpointed forward run (every 50 steps, and with
@@ -272,7 +274,7 @@ def crop_runs():
     return out
 
 
-def batched_leg(reps: int):
+def batched_leg(reps: int, single_launch: bool = True):
     import numpy as np
     import torch
 
@@ -303,7 +305,7 @@ def batched_leg(reps: int):
 
     stream = torch.cuda.Stream()
     t = time.perf_counter()
-    choice = autotune.tune_batch(props, srcs, stream, log=log)
+    choice = autotune.tune_batch(props, srcs, stream, log=log, single_launch=single_launch)
     t_tune = time.perf_counter() - t
     b = wave.Batch(props, stream=stream, use_graph=True)
     b.set_schedule(choice["schedule"], choice["nstreams"])
@@ -326,8 +328,39 @@ def batched_leg(reps: int):
     equal = all(torch.equal(a, pr.traces) for a, pr in zip(seq_traces, props))
     b.close()
 
-    # the 32 shots in one launch: every shot with the same kernel (the one
-    # the tuner chose for most cells, or the 128x16 tile), schedule 3
+    one = None
+    if single_launch:
+        one = one_launch_run(props, shots, srcs, stream, choice, nt, reps, points, seq_traces, t_seq)
+    for pr in props:
+        pr.close()
+    gpts = points * nt / t_batch / 1e9
+    sched = {0: "one persistent launch per step and kernel group",
+             3: "one launch per kernel group for the whole run (grid barrier between steps)"}.get(
+        choice["schedule"], f"every shot with its own tuned kernel on {choice['nstreams']} streams")
+    log(f"batched ({sched}): 32 shots in {t_batch * 1e3:.1f} ms ({32 / t_batch:.1f} shots/s, "
+        f"{gpts:.1f} Gpts/s); sequential {t_seq * 1e3:.1f} ms; speedup {t_seq / t_batch:.2f}x; "
+        f"traces equal: {equal}; tuning {t_tune:.1f} s")
+    return {"workload": "32 shots (seed 2207), 96..320 x 96..320 x 96..256, 3..6 layers, "
+                        "10..20 Hz Ricker, 20-cell sponge, 128 receivers, 600 steps, FP32",
+            "shots_per_s": round(32 / t_batch, 3), "value": round(gpts, 3), "unit": "Gpts/s",
+            "batched_ms": round(t_batch * 1e3, 2), "sequential_ms": round(t_seq * 1e3, 2),
+            "speedup_vs_sequential": round(t_seq / t_batch, 3), "graph": True,
+            "schedule": choice["schedule"], "schedule_name": sched, "nstreams": choice["nstreams"],
+            "tuning_us_per_step": {k: (round(v, 1) if v is not None else None)
+                                   for k, v in choice["us_per_step"].items()},
+            "launch_groups": groups if choice["schedule"] in (0, 3) else None,
+            "traces_bitwise_equal_to_sequential": bool(equal),
+            "one_launch": one,
+            "repeats": reps}
+
+
+def one_launch_run(props, shots, srcs, stream, choice, nt, reps, points, seq_traces, t_seq):
+    """The 32 shots in one launch: every shot with the same kernel (the one
+    the tuner chose for most cells, or the 128x16 tile), schedule 3."""
+    import torch
+
+    from paper_2204_03775_amd import wave
+
     names = {}
     for p_, pr in zip(shots, props):
         v, zc, _ = pr.config()
@@ -359,30 +392,11 @@ def batched_leg(reps: int):
     b1.close()
     log(f"batched in one launch ({common}, {one_groups} group): {t_one * 1e3:.1f} ms "
         f"({32 / t_one:.1f} shots/s, {points * nt / t_one / 1e9:.1f} Gpts/s); traces equal: {equal1}")
-    for pr in props:
-        pr.close()
-    gpts = points * nt / t_batch / 1e9
-    sched = {0: "one persistent launch per step and kernel group",
-             3: "one launch per kernel group for the whole run (grid barrier between steps)"}.get(
-        choice["schedule"], f"every shot with its own tuned kernel on {choice['nstreams']} streams")
-    log(f"batched ({sched}): 32 shots in {t_batch * 1e3:.1f} ms ({32 / t_batch:.1f} shots/s, "
-        f"{gpts:.1f} Gpts/s); sequential {t_seq * 1e3:.1f} ms; speedup {t_seq / t_batch:.2f}x; "
-        f"traces equal: {equal}; tuning {t_tune:.1f} s")
-    return {"workload": "32 shots (seed 2207), 96..320 x 96..320 x 96..256, 3..6 layers, "
-                        "10..20 Hz Ricker, 20-cell sponge, 128 receivers, 600 steps, FP32",
-            "shots_per_s": round(32 / t_batch, 3), "value": round(gpts, 3), "unit": "Gpts/s",
-            "batched_ms": round(t_batch * 1e3, 2), "sequential_ms": round(t_seq * 1e3, 2),
-            "speedup_vs_sequential": round(t_seq / t_batch, 3), "graph": True,
-            "schedule": choice["schedule"], "schedule_name": sched, "nstreams": choice["nstreams"],
-            "tuning_us_per_step": {k: round(v, 1) for k, v in choice["us_per_step"].items()},
-            "launch_groups": groups if choice["schedule"] in (0, 3) else None,
-            "traces_bitwise_equal_to_sequential": bool(equal),
-            "one_launch": {"schedule": 3, "kernel": common, "launch_groups": one_groups,
-                           "ms": round(t_one * 1e3, 2), "shots_per_s": round(32 / t_one, 3),
-                           "gpts_per_s": round(points * nt / t_one / 1e9, 3),
-                           "speedup_vs_sequential": round(t_seq / t_one, 3),
-                           "traces_bitwise_equal_to_sequential": bool(equal1)},
-            "repeats": reps}
+    return {"schedule": 3, "kernel": common, "launch_groups": one_groups,
+            "ms": round(t_one * 1e3, 2), "shots_per_s": round(32 / t_one, 3),
+            "gpts_per_s": round(points * nt / t_one / 1e9, 3),
+            "speedup_vs_sequential": round(t_seq / t_one, 3),
+            "traces_bitwise_equal_to_sequential": bool(equal1)}
 
 
 def gradient_leg(reps: int):
@@ -504,7 +518,7 @@ def gradient_leg(reps: int):
             "repeats": reps}, crop_out
 
 
-def launch_leg(reps: int):
+def launch_leg(reps: int, single_launch: bool = True):
     """The 64^3 x 100-step parity shot, launch-bound: eager launches
     against graph replay (wave_set_graph), ms per shot."""
     import torch
@@ -535,10 +549,20 @@ def launch_leg(reps: int):
     t_graph = timed()
     prop.close()
     log(f"launch: 64^3 x {p.nt}: eager {t_eager * 1e3:.3f} ms/shot, graph {t_graph * 1e3:.3f} ms/shot")
+    # what a launch per step is weighed against: synchronising the
+    # work-groups of one launch between steps instead
+    sync = None
+    if single_launch:
+        from paper_2204_03775_amd import probe
+
+        sync = probe.measure_sync()
+        log(f"launch: in-launch step synchronisation {sync}")
     return {"workload": "64^3 x 100 steps FP32 (the parity shot), 16 receivers",
             "eager_ms_per_shot": round(t_eager * 1e3, 4), "graph_ms_per_shot": round(t_graph * 1e3, 4),
             "graph_speedup": round(t_eager / t_graph, 3),
-            "graph_gpts_per_s": round(p.points * p.nt / t_graph / 1e9, 3), "repeats": reps}
+            "graph_us_per_step": round(t_graph / p.nt * 1e6, 3),
+            "graph_gpts_per_s": round(p.points * p.nt / t_graph / 1e9, 3),
+            "in_launch_sync_us_per_step": sync, "repeats": reps}
 
 
 # The paper's measurements for its scaling shapes, for context beside the
@@ -652,6 +676,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16 storage forms")
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-shot batched run")
+    ap.add_argument("--no-single-launch", action="store_true",
+                    help="leave cooperative launches out (the single-launch batch schedule and the "
+                         "in-launch synchronisation probe): rocprofv3 does not survive them")
     ap.add_argument("--no-gradient", action="store_true", help="skip the adjoint gradient leg")
     ap.add_argument("--no-launch", action="store_true", help="skip the 64^3 graph-replay leg")
     ap.add_argument("--no-paper-shapes", action="store_true",
@@ -752,15 +779,16 @@ def main() -> int:
     batched = None
     if not args.no_batched and args.workload == "large_shot":
         prop.close()
-        batched = batched_leg(max(1, args.steps // 2))
+        batched = batched_leg(max(1, args.steps // 2), single_launch=not args.no_single_launch)
+        one = batched["one_launch"]
         if not (batched["traces_bitwise_equal_to_sequential"]
-                and batched["one_launch"]["traces_bitwise_equal_to_sequential"]):
+                and (one is None or one["traces_bitwise_equal_to_sequential"])):
             log("error: batched traces differ from the sequential runs")
             return 1
 
     launch = None
     if not args.no_launch and args.workload == "large_shot":
-        launch = launch_leg(20)
+        launch = launch_leg(20, single_launch=not args.no_single_launch)
 
     paper_shapes = None
     if not args.no_paper_shapes and args.workload == "large_shot":

@@ -3,7 +3,9 @@
  *
  * Not part of the propagator: plain streaming kernels of known traffic,
  * used to measure the HBM bandwidth this GPU actually sustains for the
- * propagator's access pattern and to calibrate hardware byte counters.
+ * propagator's access pattern and to calibrate hardware byte counters, and
+ * the cost of synchronising work-groups inside one launch against that of
+ * a launch.
  * All pointers are device pointers of n floats (16-byte aligned, n a
  * multiple of 4); work is enqueued on `stream` and not waited for.
  * Return 0, or -1 for bad arguments / -5 for a failed launch.
@@ -30,6 +32,20 @@ int probe_read3_write1(const float *a, const float *b, const float *c, float *d,
  * (36 bytes), the access mix of one fused adjoint-and-imaging update. */
 int probe_adjoint_mix(const float *a, const float *b, const float *c, const float *d, double *g,
                       float *o, int64_t n, void *stream);
+
+/* Synchronisation cost inside one cooperative launch of `blocks` (>= 2)
+ * work-groups of 256 threads: nsteps grid-wide barriers (ring = 0) or waits
+ * for the two ring neighbours' step counters (ring != 0), each work-group
+ * arriving with an agent-scope release and leaving after an agent-scope
+ * acquire, as the library's single-launch batch does between steps.
+ * words: device ints, at least 4 + blocks, all zero on entry; words[2] is
+ * raised (and the launch ends) if a wait passes timeout_s seconds of wall
+ * clock.  -1 for bad arguments or a device without cooperative launches,
+ * -5 if the launch fails (for instance more work-groups than fit at once). */
+int probe_sync(int *words, int blocks, int nsteps, int ring, double timeout_s, void *stream);
+
+/* An empty kernel of `blocks` work-groups: the cost of a launch. */
+int probe_empty(int blocks, void *stream);
 
 #ifdef __cplusplus
 }

@@ -181,23 +181,25 @@ def tune_single(prop, src, stream, nsteps: int = 20, use_cache: bool = True, log
     return name, zc
 
 
-def tune_batch(props, srcs, stream, nsteps: int = 30, use_cache: bool = True, log=None) -> dict:
+def tune_batch(props, srcs, stream, nsteps: int = 30, use_cache: bool = True, log=None,
+               single_launch: bool = True) -> dict:
     """Choose how to run this batch: schedule 0 (one persistent launch per
     step and group) or schedule 3 (one launch per group for the whole run)
     with a (variant, chunks) per size class, or schedule 1 (every shot with
     its own tuned configuration on 1, 2 or 4 streams), whichever is fastest.  Configures the Propagators and returns
     {"schedule", "nstreams", "classes" or "shots", "us_per_step"}; create
-    the Batch afterwards and call its set_schedule(schedule, nstreams)."""
+    the Batch afterwards and call its set_schedule(schedule, nstreams).
+    ``single_launch=False`` leaves schedule 3 (a cooperative launch) out."""
     classes = tune_classes(props, srcs, stream, nsteps, use_cache, log)
     t_queue = time_batch(props, srcs, nsteps, stream)
-    t_run = time_batch(props, srcs, nsteps, stream, schedule=3)
+    t_run = time_batch(props, srcs, nsteps, stream, schedule=3) if single_launch else float("inf")
     shots = [tune_single(p, s, stream, use_cache=use_cache, log=log) for p, s in zip(props, srcs)]
     t_streams = {k: time_batch(props, srcs, nsteps, stream, schedule=1, nstreams=k) for k in STREAM_COUNTS}
     k_best = min(t_streams, key=t_streams.get)
     if log:
         log(f"tune batch: schedule 0 {t_queue * 1e6:.1f} us/step; schedule 3 {t_run * 1e6:.1f}; schedule 1 "
             + ", ".join(f"{k} streams {t * 1e6:.1f}" for k, t in t_streams.items()) + " us/step")
-    times = {"schedule0": t_queue * 1e6, "schedule3": t_run * 1e6,
+    times = {"schedule0": t_queue * 1e6, "schedule3": t_run * 1e6 if single_launch else None,
              **{f"schedule1_streams{k}": t * 1e6 for k, t in t_streams.items()}}
     if t_streams[k_best] < min(t_queue, t_run):
         return {"schedule": 1, "nstreams": k_best, "shots": [list(x) for x in shots],

@@ -122,6 +122,70 @@ __global__ __launch_bounds__(kThreads) void adjmix_k(const f4 *__restrict__ a, c
     }
 }
 
+// Synchronisation between work-groups of one cooperative launch, as the
+// library's single-launch batch does it between steps: nsteps barriers
+// across the whole grid (ring = 0), or waits for the two ring neighbours'
+// step counters (ring = 1), each work-group arriving with an agent-scope
+// release and leaving after an agent-scope acquire.  words: [0] arrivals,
+// [1] barriers opened, [2] abort, [3] spare, [4 + b] steps done by
+// work-group b; all zero at launch.  Every wait gives up once the wall
+// clock passes the deadline and raises words[2].
+__global__ __launch_bounds__(256) void sync_k(int *words, int nsteps, int ring, unsigned long long timeout)
+{
+    __shared__ int stop;
+    const unsigned long long deadline = wall_clock64() + timeout;
+    unsigned *count = reinterpret_cast<unsigned *>(words);
+    unsigned *gen = reinterpret_cast<unsigned *>(words + 1);
+    int *abort = words + 2;
+    int *done = words + 4;
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int l = (b + nb - 1) % nb, r = (b + 1) % nb;
+    auto give_up = [&]() {
+        return wall_clock64() > deadline || __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    unsigned g = 0;
+    for (int j = 0; j < nsteps; ++j) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            stop = 0;
+            if (ring) {
+                __hip_atomic_store(done + b, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                while (__hip_atomic_load(done + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= j ||
+                       __hip_atomic_load(done + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= j) {
+                    if (give_up()) {
+                        stop = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            } else {
+                const unsigned a = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                if (a + 1 == (unsigned)nb) {
+                    __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                        if (give_up()) {
+                            stop = 1;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                ++g;
+            }
+            if (stop)
+                __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        if (stop)
+            return;
+    }
+}
+
+__global__ void empty_k() {}
+
 bool bad(const void *p) { return !p || (reinterpret_cast<uintptr_t>(p) & 15u); }
 
 int grid_for(long long n4)
@@ -165,5 +229,29 @@ extern "C" int probe_adjoint_mix(const float *a, const float *b, const float *c,
     const long long n4 = n / 4;
     hipLaunchKernelGGL(adjmix_k, dim3(grid_for(n4)), dim3(kThreads), 0, (hipStream_t)stream,
                        (const f4 *)a, (const f4 *)b, (const f4 *)c, (const f4 *)d, (d2 *)g, (f4 *)o, n4);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+extern "C" int probe_sync(int *words, int blocks, int nsteps, int ring, double timeout_s, void *stream)
+{
+    int dev = 0, khz = 0, coop = 0;
+    if (!words || blocks < 2 || nsteps < 0 || !(timeout_s >= 0.0) ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop || khz < 1)
+        return -1;
+    unsigned long long timeout = (unsigned long long)(timeout_s * khz * 1000.0);
+    void *args[] = {&words, &nsteps, &ring, &timeout};
+    if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(sync_k), dim3(blocks), dim3(256), args, 0,
+                                   (hipStream_t)stream) != hipSuccess)
+        return -5;
+    return 0;
+}
+
+extern "C" int probe_empty(int blocks, void *stream)
+{
+    if (blocks < 1)
+        return -1;
+    hipLaunchKernelGGL(empty_k, dim3(blocks), dim3(256), 0, (hipStream_t)stream);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }

@@ -4,6 +4,8 @@
 the copy (1 read + 1 write) and read3-write1 (the propagator's per-update
 access mix) bandwidth in GB/s, for arrays of ``elements`` floats each
 (default: one 512^3 field in the propagator's padded layout).
+``measure_sync`` gives the cost of synchronising work-groups inside one
+launch, against that of a launch.
 """
 from __future__ import annotations
 
@@ -29,7 +31,58 @@ def _load():
     lib.probe_read3_write1.restype = ctypes.c_int
     lib.probe_adjoint_mix.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
     lib.probe_adjoint_mix.restype = ctypes.c_int
+    ci = ctypes.c_int
+    lib.probe_sync.argtypes = [vp, ci, ci, ci, ctypes.c_double, vp]
+    lib.probe_sync.restype = ci
+    lib.probe_empty.argtypes = [ci, vp]
+    lib.probe_empty.restype = ci
     return lib
+
+
+def measure_sync(nsteps: int = 2000) -> dict:
+    """Microseconds per step of synchronising all work-groups of one
+    cooperative launch (a grid barrier, or waits for two ring neighbours),
+    at one and two 256-thread work-groups per CU, against the cost of an
+    empty launch of as many work-groups."""
+    lib = _load()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    stream = torch.cuda.current_stream()
+    s = stream.cuda_stream
+
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps
+
+    out = {"steps": nsteps}
+    for per in (1, 2):
+        blocks = per * cus
+        words = torch.zeros(4 + blocks, dtype=torch.int32, device="cuda")
+        for ring, name in ((0, "grid_barrier"), (1, "neighbour_flags")):
+            words.zero_()
+            torch.cuda.synchronize()
+
+            def run():
+                rc = lib.probe_sync(words.data_ptr(), blocks, nsteps, ring, 10.0, s)
+                if rc != 0:
+                    raise RuntimeError(f"probe_sync failed (code {rc})")
+
+            us = timed(run, 1) / nsteps
+            if int(words[2].item()):
+                raise RuntimeError("probe_sync: a wait gave up")
+            out[f"{name}_us_{per}wg_per_cu"] = round(us, 3)
+
+        def empty():
+            if lib.probe_empty(blocks, s) != 0:
+                raise RuntimeError("probe_empty failed")
+
+        empty()
+        out[f"empty_launch_us_{per}wg_per_cu"] = round(timed(empty, nsteps), 3)
+    return out
 
 
 def measure(n: int, repeats: int = 20, with_adjoint_mix: bool = False) -> dict:

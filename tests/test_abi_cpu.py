@@ -27,6 +27,23 @@ def test_every_declared_symbol_is_exported(w):
         assert hasattr(lib, n), n
 
 
+def test_every_probe_symbol_is_exported(w):
+    # include/wave_probe.h declares the measurement probes of libwave_probe.so
+    import os
+
+    header = os.path.join(os.path.dirname(w.HEADER), "wave_probe.h")
+    text = re.sub(r"/\*.*?\*/", "", open(header).read(), flags=re.S)
+    names = sorted(set(re.findall(r"^\s*int\s+(probe_[a-z_0-9]+)\s*\(", text, flags=re.M)))
+    assert {"probe_copy", "probe_read3_write1", "probe_adjoint_mix", "probe_sync", "probe_empty"} <= set(names)
+    from paper_2204_03775_amd import probe
+
+    lib = probe._load()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.probe_sync(None, 256, 10, 0, 1.0, None) == -1  # rejected before any launch
+    assert lib.probe_empty(0, None) == -1
+
+
 def test_single_hip_runtime_in_process(w):
     maps = open("/proc/self/maps").read()
     paths = set(re.findall(r"\S*libamdhip64\S*", maps))
