@@ -28,6 +28,11 @@ Parity status per function (what pins it lives in ``tests/test_oracle_*``):
                    ``tangent`` to FP64 rounding)
   tangent          pinned (central finite differences of the traces computed
                    with ``run``, converging as eps^2)
+  run16            the 16-bit storage forms (an extension of the paper's FP32
+                   scheme) emulated in FP32: codecs pinned against numpy's
+                   binary16 and an independent nearest-even bfloat16
+                   rounding; each step against the FP64 update of its own
+                   decoded inputs; exact power-of-two equivariance
 """
 from __future__ import annotations
 
@@ -84,6 +89,18 @@ def _load():
     lib.oracle_tangent.argtypes = [ci, ci, ci, cd, cd, cd, ci, cd, dp, dp, ci, dp, ci, ci, ci, ci, ip,
                                    dp, ci]
     lib.oracle_tangent.restype = ci
+    u16p = ctypes.POINTER(ctypes.c_uint16)
+    lib.oracle16_run.argtypes = [ci, ci, ci, cd, cd, cd, ci, cd, ci, fp, ci, fp, ci, ci, ci, ci, ip, u16p, u16p,
+                                 ip, fp]
+    lib.oracle16_run.restype = ci
+    lib.oracle16_f16_encode.argtypes = [ctypes.c_float]
+    lib.oracle16_f16_encode.restype = ctypes.c_uint16
+    lib.oracle16_f16_decode.argtypes = [ctypes.c_uint16]
+    lib.oracle16_f16_decode.restype = ctypes.c_float
+    lib.oracle16_bf16_encode.argtypes = [ctypes.c_float]
+    lib.oracle16_bf16_encode.restype = ctypes.c_uint16
+    lib.oracle16_bf16_decode.argtypes = [ctypes.c_uint16]
+    lib.oracle16_bf16_decode.restype = ctypes.c_float
     _lib = lib
     return lib
 
@@ -190,6 +207,51 @@ def run_segments(k: np.ndarray, h, nt: int, segment: int, *, s=None, progress=No
         a_cur, a_prev, tr = run(k, h, 0, s=s, **kw)
         rows.append(tr)
     return a_cur, a_prev, np.concatenate(rows, axis=0), sec
+
+
+FORMS16 = {"f16": 1, "bf16": 2, "f16uv": 3, "bf16uv": 4}
+
+
+def codec16(form: str):
+    """(encode, decode) of one 16-bit value for "f16" or "bf16" (scalar
+    functions of the emulation, for its own pins)."""
+    lib = _load()
+    if form == "f16":
+        return lib.oracle16_f16_encode, lib.oracle16_f16_decode
+    return lib.oracle16_bf16_encode, lib.oracle16_bf16_decode
+
+
+def run16(k32, h, nt: int, form: str, *, s=None, src=None, rec=None, sponge_width: int = 0,
+          sponge_alpha: float = 0.0):
+    """The 16-bit storage forms emulated in FP32 on the CPU (oracle16.c):
+    ``nt`` steps from zero fields with FP32 k ``k32`` [nz][ny][nx] and FP32
+    source values ``s``.  Returns (stored u^nt bits [nz][ny][nx] uint16,
+    stored d^nt bits or None, exponents [nt] of u^1..u^nt, traces [nt][nrec]
+    FP32)."""
+    k32 = np.ascontiguousarray(k32, dtype=np.float32)
+    nz, ny, nx = k32.shape
+    dx, dy, dz = h
+    f = FORMS16[form]
+    rec = np.zeros((0, 3), dtype=np.int32) if rec is None else np.ascontiguousarray(rec, dtype=np.int32).reshape(-1, 3)
+    nrec = rec.shape[0]
+    u = np.zeros((nz, ny, nx), dtype=np.uint16)
+    d = np.zeros((nz, ny, nx), dtype=np.uint16) if f >= 3 else None
+    exps = np.zeros(max(nt, 0), dtype=np.int32)
+    traces = np.zeros((max(nt, 0), nrec), dtype=np.float32)
+    sp = None
+    if s is not None:
+        s = np.ascontiguousarray(s, dtype=np.float32)
+        assert s.shape[0] >= nt
+        sp = _fptr(s)
+    sz, sy, sx = src if src is not None else (-1, -1, -1)
+    u16 = ctypes.POINTER(ctypes.c_uint16)
+    rc = _load().oracle16_run(nx, ny, nz, dx, dy, dz, int(sponge_width), float(sponge_alpha), f, _fptr(k32),
+                              int(nt), sp, int(sz), int(sy), int(sx), nrec, _iptr(rec),
+                              u.ctypes.data_as(u16), d.ctypes.data_as(u16) if d is not None else None,
+                              _iptr(exps), _fptr(traces))
+    if rc != 0:
+        raise ValueError(f"oracle16_run rejected its arguments (rc={rc})")
+    return u, d, exps, traces
 
 
 def step_points(k32, u_cur32, u_prev32, h, pts, *, sponge_width=0, sponge_alpha=0.0,
