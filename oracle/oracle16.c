@@ -203,8 +203,10 @@ int oracle16_run(int nx, int ny, int nz, double dx, double dy, double dz, int sp
     uint16_t *cur = calloc(np, 2), *sec = calloc(np, 2), *nxt = calloc(np, 2), *nd = calloc(np, 2),
              *kq = calloc(np, 2);
     float *gx = malloc(sizeof(float) * nx), *gy = malloc(sizeof(float) * ny), *gz = malloc(sizeof(float) * nz);
-    if (!cur || !sec || !nxt || !nd || !kq || !gx || !gy || !gz) {
-        free(cur); free(sec); free(nxt); free(nd); free(kq); free(gx); free(gy); free(gz);
+    /* u^n decoded (decoding is exact, so reading it equals decoding each read) */
+    float *curf = malloc(sizeof(float) * np);
+    if (!cur || !sec || !nxt || !nd || !kq || !gx || !gy || !gz || !curf) {
+        free(cur); free(sec); free(nxt); free(nd); free(kq); free(gx); free(gy); free(gz); free(curf);
         return -2;
     }
 #define PI(z, y, x) (((size_t)((z) + G) * nyp + (size_t)((y) + G)) * nxp + (size_t)((x) + G))
@@ -259,21 +261,23 @@ int oracle16_run(int nx, int ny, int nz, double dx, double dy, double dz, int sp
         }
         const float two_a = 2.0f * A;
         const float sval = sv * out_inv;
+        for (size_t i = 0; i < np; ++i)
+            curf[i] = dec16(bf, cur[i]);
         float m_new = 0.0f;
+        /* cells are independent within a step; a maximum does not depend on
+         * the order it is taken in */
+#pragma omp parallel for reduction(max : m_new) schedule(static)
         for (int z = 0; z < nz; ++z)
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x) {
                     const size_t p = PI(z, y, x);
-                    const float U = dec16(bf, cur[p]);
+                    const float U = curf[p];
                     float lap = v0 * U;
                     for (int m = 1; m <= 4; ++m) {
-                        lap = fmaf(vx[m], dec16(bf, cur[p + m]) + dec16(bf, cur[p - m]), lap);
-                        lap = fmaf(vy[m], dec16(bf, cur[p + (size_t)m * nxp]) + dec16(bf, cur[p - (size_t)m * nxp]),
-                                   lap);
-                        lap = fmaf(vz[m],
-                                   dec16(bf, cur[p + (size_t)m * nxp * nyp]) +
-                                       dec16(bf, cur[p - (size_t)m * nxp * nyp]),
-                                   lap);
+                        const size_t sy = (size_t)m * nxp, sz = (size_t)m * nxp * nyp;
+                        lap = fmaf(vx[m], curf[p + m] + curf[p - m], lap);
+                        lap = fmaf(vy[m], curf[p + sy] + curf[p - sy], lap);
+                        lap = fmaf(vz[m], curf[p + sz] + curf[p - sz], lap);
                     }
                     const float K = dec16(bf, kq[p]);
                     const float P = dec16(bf, sec[p]);
@@ -320,6 +324,6 @@ int oracle16_run(int nx, int ny, int nz, double dx, double dy, double dz, int sp
                     d_bits[((size_t)z * ny + y) * nx + x] = sec[PI(z, y, x)];
             }
 #undef PI
-    free(cur); free(sec); free(nxt); free(nd); free(kq); free(gx); free(gy); free(gz);
+    free(cur); free(sec); free(nxt); free(nd); free(kq); free(gx); free(gy); free(gz); free(curf);
     return 0;
 }

@@ -8,7 +8,11 @@ Exact checks:
     unchanged and multiplies every decoded field value and trace by 2^j,
     bit for bit wherever the decoded value is an FP32 normal (BF16 keeps
     FP32's exponent range, so decoding can land in the subnormals, where a
-    power-of-two scaling is not exact; there the values agree to FLT_MIN).
+    power-of-two scaling is not exact; there the values agree to FLT_MIN);
+  - the stored bits, level exponent and traces equal, bit for bit, those of
+    the CPU emulation of the scheme in oracle/oracle16.c (pinned on its own
+    against numpy's float16, nearest-even bfloat16 rounding and the FP64
+    update of its decoded inputs), on a ragged grid and on the 128^3 crop.
 Accuracy against the FP64 oracle (relative L2 on field and traces), bounds
 stated per format from the formats' unit roundoff (FP16 2^-11, BF16 2^-8)
 and the measured error growth:
@@ -161,3 +165,49 @@ def test_stored_magnitude_stays_below_two_to_fourteen(wave_mod, ragged, dtype):
         m = prop.interior(cur).float().abs().max().item()
         assert np.isfinite(m) and m < 2.0 ** 14
     prop.close()
+
+
+def emulation_check(wave, oracle_lib, p, dtype):
+    # the GPU's stored 16-bit field, its level exponent and its traces against
+    # the CPU emulation of the same scheme (oracle/oracle16.c: FP32 arithmetic
+    # in the documented order, its own codecs and exponent rule), both run
+    # for the same steps from zero fields; in the u-and-change forms d^n
+    # enters every later level, so equal levels pin it up to the last step
+    s32 = p.s.astype(np.float32)
+    print(f"case: {dtype} {p.nx}x{p.ny}x{p.nz} x {p.nt} steps against the emulation", flush=True)
+    prop = wave.Propagator(p.nx, p.ny, p.nz, p.h, p.k32(), src=p.src, rec=p.rec,
+                           sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha, dtype=dtype)
+    prop.record(p.nt)
+    prop.run(p.nt, torch.tensor(s32, device="cuda"))
+    cur, _, n = prop.fields()
+    bits = prop.interior(cur).view(torch.int16).cpu().numpy().view(np.uint16).copy()
+    dec = prop.export(0).cpu().numpy()
+    prop.sync()
+    tr = prop.traces.cpu().numpy()[:, :prop.nrec]
+    prop.close()
+    assert n == p.nt
+    u, _, exps, rtr = oracle_lib.run16(p.k32(), p.h, p.nt, dtype, s=s32, src=p.src, rec=p.rec,
+                                       sponge_width=p.sponge_width, sponge_alpha=p.sponge_alpha)
+    diff = int(np.count_nonzero(bits != u))
+    # the GPU's exponent of the last level: decoded export over stored value
+    _, dec16 = oracle_lib.codec16("bf16" if dtype.startswith("bf16") else "f16")
+    i = np.unravel_index(np.argmax(np.abs(dec)), dec.shape)
+    e_gpu = int(np.round(np.log2(abs(float(dec[i])) / abs(dec16(int(bits[i]))))))
+    print(f"{dtype}: {diff} of {bits.size} stored values differ; exponent GPU {e_gpu}, emulation {exps[-1]}; "
+          f"traces equal: {np.array_equal(tr, rtr)}")
+    assert diff == 0
+    assert e_gpu == exps[-1]
+    assert np.array_equal(tr, rtr)
+
+
+@pytest.mark.parametrize("dtype", LOWP)
+def test_bitwise_equal_to_cpu_emulation(wave_mod, oracle_lib, ragged, dtype):
+    emulation_check(wave_mod, oracle_lib, ragged, dtype)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("dtype", LOWP)
+def test_crop_bitwise_equal_to_cpu_emulation(wave_mod, oracle_lib, crop, dtype):
+    # 128^3, 500 steps, sponge 20 cells: several tiles and chunks, and the
+    # exponent rule over hundreds of levels (the emulation takes ~10-20 s)
+    emulation_check(wave_mod, oracle_lib, crop, dtype)
