@@ -165,6 +165,7 @@ struct wave_ctx {
     void *dbuf = nullptr;                   // d^n (u-and-change storage), library-owned
     void *cur = nullptr, *prev = nullptr;
     int64_t step = 0;
+    unsigned zflip = 0;  // tiled launches so far: their z-march directions alternate
     int src[3] = {-1, -1, -1};
     std::vector<int32_t> rec;  // [nrec][3]
     int nrec = 0;
@@ -493,6 +494,7 @@ StepArgs make_args(const wave_ctx *c)
     a.grad = nullptr;
     a.aux = nullptr;
     a.dlt = c->dbuf;
+    a.zdown = 0;
     return a;
 }
 
@@ -509,6 +511,7 @@ int enqueue_forward(wave_ctx *c, void *cur, void *prev, void *out, const float *
     a.src_val = src_val;
     a.step = int(step & 0x3fffffff);
     a.trace_row = trace_row;
+    a.zdown = int(c->zflip++ & 1u);
 
     const int kind = c->p.dtype;
     if (c->v_used == kNaive) {
@@ -685,6 +688,7 @@ int enqueue_adjoint(wave_ctx *c, const Geo &geo, int mode, const void *cur, void
     a.src_z = a.src_y = a.src_x = -1;
     a.src_ptr = nullptr;
     a.trace_row = nullptr;
+    a.zdown = int(c->zflip++ & 1u);
     const Variant &V = kVariants[geo.v];
     hipLaunchKernelGGL(V.adj[mode - 1], dim3(geo.grid), dim3(V.txv * V.ty), 0, c->stream, a);
     hipError_t e = hipGetLastError();

@@ -74,6 +74,12 @@ struct StepArgs {
     const void *aux;
     // u-and-change storage: d^n on entry, d^{n+1} on exit (same cells, same thread)
     void *dlt;
+    // z-march direction of the tiled kernels: 0 up, 1 down.  Consecutive
+    // launches alternate, so that a launch starts on the planes the one
+    // before touched last, which the GPU's memory-side cache still holds.
+    // The results do not depend on it: the z taps enter only as the
+    // commutative sums u[z+m] + u[z-m].
+    int zdown;
 };
 
 // What a tiled launch computes (FP32 storage only for the last two):

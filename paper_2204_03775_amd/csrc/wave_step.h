@@ -51,6 +51,17 @@ __device__ __forceinline__ float src_value(const StepArgs &a)
     return a.src_ptr ? a.src_ptr[0] : a.src_val;
 }
 
+// x * g rounded on its own.  The adjoint scales every loaded value by the
+// sponge factor; if that product were contracted into the first sum that
+// uses it (an FMA), the value would enter that sum unrounded and the other
+// operand rounded, so the result would depend on which of u[z+m], u[z-m]
+// was loaded last, i.e. on the direction of the z-march.
+__device__ __forceinline__ float mul_rounded(float x, float g)
+{
+#pragma clang fp contract(off)
+    return x * g;
+}
+
 // Work-groups are handed to the 8 XCDs round-robin by block index (the
 // starting XCD follows on from the previous launch, so blocks with equal
 // b % 8 share an XCD, not necessarily XCD b % 8); map block b to logical
@@ -374,6 +385,11 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
     const int ch = rest / a.nty;
     const int z0 = ch * a.zc;
     const int z1 = min(z0 + a.zc, a.nz);
+    // the chunk's planes in march order: march position l is plane zp(l)
+    // (positions -4 .. -1 and len .. len + 3 are the chunk's z halo)
+    const int len = z1 - z0;
+    const bool down = a.zdown & 1;
+    auto zp = [&](int l) { return down ? z1 - 1 - l : z0 + l; };
 
     const int tid = threadIdx.x;
     const int lx = tid % TXV;
@@ -496,7 +512,8 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
     const __amdgpu_buffer_rsrc_t gz_r = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<float *>(a.gz), (short)0, a.nz * (int)sizeof(float), kRsrcWord3);
 
-    // register queue: at phase s the plane z - 4 + i lives in slot (s + i) % QS
+    // register queue: at phase s the plane of march position l - 4 + i
+    // lives in slot (s + i) % QS
     auto gz_at = [&](int z) {  // g_z, zero outside the interior (reads nothing there)
         return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(gz_r, 4u * unsigned(z), 0, 0));
     };
@@ -504,23 +521,24 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
     f4 q2[FUS ? QS : 1][RY];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const __amdgpu_buffer_rsrc_t rc = stencil_plane_rsrc(a.cur, pbytes, z0 - 4 + i, a.nz);
+        const int zi = zp(i - 4);
+        const __amdgpu_buffer_rsrc_t rc = stencil_plane_rsrc(a.cur, pbytes, zi, a.nz);
 #pragma unroll
         for (int r = 0; r < RY; ++r)
             q[i][r] = load4<KIND, PK>(rc, own_ld[r], 1.f);
         if constexpr (FUS) {
-            const __amdgpu_buffer_rsrc_t ra = stencil_plane_rsrc(a.aux, pbytes, z0 - 4 + i, a.nz);
+            const __amdgpu_buffer_rsrc_t ra = stencil_plane_rsrc(a.aux, pbytes, zi, a.nz);
 #pragma unroll
             for (int r = 0; r < RY; ++r)
                 q2[i][r] = load4<KIND, PK>(ra, own_ld[r], 1.f);
         }
         if constexpr (ADJ) {
-            const float gzi = gz_at(z0 - 4 + i);
+            const float gzi = gz_at(zi);
 #pragma unroll
             for (int r = 0; r < RY; ++r)
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    q[i][r].v[e] *= gown[r].v[e] * gzi;
+                    q[i][r].v[e] = mul_rounded(q[i][r].v[e], gown[r].v[e] * gzi);
         }
     }
 
@@ -528,9 +546,10 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
     // other parity (no copies, so no wait before the next loads are issued)
     Raw4<KIND> pv[2][RY], kv[2][RY], hv[2][HPT];
     f4 hv2[FUS ? 2 : 1][FUS ? HPT : 1];
-    float gzv[2], gzq[2];  // g_z of the plane and (adjoint) of the queue plane z + 4
-    auto prefetch = [&](int z, int slot, int set) {
-        const __amdgpu_buffer_rsrc_t rq = stencil_plane_rsrc(a.cur, pbytes, z + 4, a.nz);
+    float gzv[2], gzq[2];  // g_z of the plane and (adjoint) of the queue plane four positions on
+    auto prefetch = [&](int l, int slot, int set) {
+        const int z = zp(l), zq = zp(l + 4);
+        const __amdgpu_buffer_rsrc_t rq = stencil_plane_rsrc(a.cur, pbytes, zq, a.nz);
         const __amdgpu_buffer_rsrc_t rp = plane_rsrc(UV ? a.dlt : a.nxt, pbytes, z);
         const __amdgpu_buffer_rsrc_t rk = plane_rsrc(a.k, pbytes, z);
         const __amdgpu_buffer_rsrc_t rh = plane_rsrc(a.cur, pbytes, z);
@@ -544,7 +563,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
         for (int h = 0; h < HPT; ++h)
             hv[set][h] = load_raw4<KIND, PK>(rh, h_b[h]);
         if constexpr (FUS) {
-            const __amdgpu_buffer_rsrc_t raq = stencil_plane_rsrc(a.aux, pbytes, z + 4, a.nz);
+            const __amdgpu_buffer_rsrc_t raq = stencil_plane_rsrc(a.aux, pbytes, zq, a.nz);
             const __amdgpu_buffer_rsrc_t rah = plane_rsrc(a.aux, pbytes, z);
 #pragma unroll
             for (int r = 0; r < RY; ++r)
@@ -555,21 +574,22 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
         }
         gzv[set] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(gz_r, 4u * z, 0, 0));
         if constexpr (ADJ)
-            gzq[set] = gz_at(z + 4);
+            gzq[set] = gz_at(zq);
     };
-    prefetch(z0, 8, 0);
+    prefetch(0, 8, 0);
 
     float tmax = 0.f;  // max |stored u^{n+1}| written by this thread (16-bit storage)
     const Coefs c = fd.c;
-    for (int zb = z0; zb < z1; zb += QS) {
+    for (int lb = 0; lb < len; lb += QS) {
         static_for_while<0, QS>([&](auto phase) __attribute__((always_inline)) -> bool {
             constexpr int s = decltype(phase)::value;
-            const int z = zb + s;
-            if (z >= z1)
+            const int l = lb + s;
+            if (l >= len)
                 return false;
+            const int z = zp(l);
             const int cur_set = s & 1;
             // next plane (clamped on the last one, whose loads go unused)
-            prefetch(min(z + 1, z1 - 1), (s + 9) % QS, cur_set ^ 1);
+            prefetch(min(l + 1, len - 1), (s + 9) % QS, cur_set ^ 1);
             // imaging modes: this plane's accumulator values, loaded before
             // the arithmetic so that their latency overlaps it; each cell is
             // read and written once per step, so both are streamed
@@ -586,15 +606,16 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
             }
 
             if constexpr (ADJ) {
-                // psi = G phi: the plane that just entered the queue (z + 4)
+                // psi = G phi: the plane that just entered the queue (four positions on)
                 // and this plane's halo
 #pragma unroll
                 for (int r = 0; r < RY; ++r)
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        q[(s + 8) % QS][r].v[e] *= gown[r].v[e] * gzq[cur_set];
+                        q[(s + 8) % QS][r].v[e] =
+                            mul_rounded(q[(s + 8) % QS][r].v[e], gown[r].v[e] * gzq[cur_set]);
             }
-            const int b = z & 1;
+            const int b = l & 1;
             f4 *L = &lds[b][0][0];
 #pragma unroll
             for (int r = 0; r < RY; ++r)
@@ -605,7 +626,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
                 if constexpr (ADJ) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        hd.v[e] *= gh[h].v[e] * gzv[cur_set];
+                        hd.v[e] = mul_rounded(hd.v[e], gh[h].v[e] * gzv[cur_set]);
                 }
                 if (h_lds[h] >= 0)
                     L[h_lds[h]] = hd;
@@ -871,6 +892,7 @@ __device__ __forceinline__ void batch_step_items(const ShotDesc *__restrict__ sh
         a.out = a.nxt;  // in place
         const int n = d.n0 + j;
         a.step = n & 0x3fffffff;
+        a.zdown = n & 1;
         a.trace_row = d.traces ? d.traces + (size_t)n * d.nrec : nullptr;
         a.src_ptr = d.src ? d.src + j : nullptr;
         a.src_val = 0.f;
@@ -1037,6 +1059,7 @@ __global__ __launch_bounds__(TXV *TY) void step_flow(const ShotDesc *__restrict_
         a.out = a.nxt;  // in place
         const int n = d.n0 + jj;
         a.step = n & 0x3fffffff;
+        a.zdown = 0;
         a.trace_row = d.traces ? d.traces + (size_t)n * d.nrec : nullptr;
         a.src_ptr = d.src ? d.src + jj : nullptr;
         a.src_val = 0.f;
