@@ -47,6 +47,19 @@ int probe_sync(int *words, int blocks, int nsteps, int ring, double timeout_s, v
 /* An empty kernel of `blocks` work-groups: the cost of a launch. */
 int probe_empty(int blocks, void *stream);
 
+/* The propagator step's HBM access pattern without its arithmetic, on three
+ * fields in the library's padded layout (nz + 8 planes of ny + 8 rows of
+ * `pitch` floats, interior x from float `x0`; 4 ghost planes and rows on
+ * each side): tiles of 256 cells x 8 rows and z-chunks of zc planes, each
+ * work-group marching its chunk (from the top when `down`), reading a four
+ * planes ahead of the march and b, k at the plane, and writing
+ * b = a + b + k in place: 16 bytes per interior cell, as one step.
+ * Launches that swap a and b and alternate `down` reproduce the library's
+ * launch sequence.  -1 for bad arguments (nx and x0 multiples of 4,
+ * x0 >= 4, pitch >= x0 + nx + 4). */
+int probe_step_stream(const float *a, float *b, const float *k, int nx, int ny, int nz, int64_t pitch,
+                      int64_t x0, int zc, int down, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -186,6 +186,53 @@ __global__ __launch_bounds__(256) void sync_k(int *words, int nsteps, int ring, 
 
 __global__ void empty_k() {}
 
+// The step's plane march without its arithmetic.  A work-group owns a tile
+// of 256 cells x 8 rows of a padded field (4 ghost planes and rows on each
+// side, rows `pitch4` float4 apart, interior x from float4 `x04`) and a
+// chunk of zc planes.  For every plane z of the chunk, in march order, it
+// reads a at the plane four ahead of the march (as the step's register queue
+// does), b and k at plane z, and writes b = a + b + k over b at plane z (the
+// step overwrites u^{n-1} in place): 16 bytes per cell.  The next plane's
+// values are loaded before the current plane is stored.  Cache policies are
+// the step's: a (u^n, which neighbouring tiles read again) with the default
+// policy, b and k read and b written non-temporally.  Work-groups are
+// mapped to tiles as the step kernels map them (contiguous runs per XCD).
+// down: every chunk is marched from its top plane.
+__global__ __launch_bounds__(512) void step_stream_k(const f4 *__restrict__ a, f4 *__restrict__ b,
+                                                     const f4 *__restrict__ k, int nx4, int ny, int nz,
+                                                     long long pitch4, long long plane4, int x04, int zc,
+                                                     int ntx, int nty, int nwg, int down)
+{
+    const int per = gridDim.x >> 3;
+    const int lid = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (lid >= nwg)
+        return;
+    const int tx = lid % ntx, rest = lid / ntx, ty = rest % nty, ch = rest / nty;
+    const int z0 = ch * zc, z1 = min(z0 + zc, nz), len = z1 - z0;
+    const int col = tx * 64 + (int)(threadIdx.x % 64), row = ty * 8 + (int)(threadIdx.x / 64);
+    if (col >= nx4 || row >= ny)
+        return;
+    const long long off = (long long)(row + 4) * pitch4 + x04 + col;
+    const int dz = down ? -1 : 1;
+    const int zs = down ? z1 - 1 : z0;
+    auto at = [&](int z) { return (long long)(z + 4) * plane4 + off; };
+    f4 an = a[at(zs + 4 * dz)], bn = ldnt(b + at(zs)), kn = ldnt(k + at(zs));
+    for (int l = 0; l < len; ++l) {
+        const int z = zs + l * dz;
+        const f4 x = an, y = bn, w = kn;
+        if (l + 1 < len) {
+            an = a[at(z + 5 * dz)];
+            bn = ldnt(b + at(z + dz));
+            kn = ldnt(k + at(z + dz));
+        }
+        f4 o;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            o.v[e] = x.v[e] + y.v[e] + w.v[e];
+        stnt(b + at(z), o);
+    }
+}
+
 bool bad(const void *p) { return !p || (reinterpret_cast<uintptr_t>(p) & 15u); }
 
 int grid_for(long long n4)
@@ -253,5 +300,23 @@ extern "C" int probe_empty(int blocks, void *stream)
     if (blocks < 1)
         return -1;
     hipLaunchKernelGGL(empty_k, dim3(blocks), dim3(256), 0, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+extern "C" int probe_step_stream(const float *a, float *b, const float *k, int nx, int ny, int nz, int64_t pitch,
+                                 int64_t x0, int zc, int down, void *stream)
+{
+    if (bad(a) || bad(b) || bad(k) || nx < 4 || (nx & 3) || ny < 1 || nz < 1 || zc < 1 || (pitch & 3) ||
+        (x0 & 3) || x0 < 4 || pitch < x0 + nx + 4)
+        return -1;
+    const int nx4 = nx / 4;
+    const int ntx = (nx4 + 63) / 64, nty = (ny + 7) / 8, nch = (nz + zc - 1) / zc;
+    const long long nwg = (long long)ntx * nty * nch;
+    if (nwg > (1ll << 30))
+        return -1;
+    const long long pitch4 = pitch / 4, plane4 = pitch4 * (ny + 8);
+    const int grid = int((nwg + 7) / 8 * 8);
+    hipLaunchKernelGGL(step_stream_k, dim3(grid), dim3(512), 0, (hipStream_t)stream, (const f4 *)a, (f4 *)b,
+                       (const f4 *)k, nx4, ny, nz, pitch4, plane4, int(x0 / 4), zc, ntx, nty, int(nwg), down ? 1 : 0);
     return hipGetLastError() == hipSuccess ? 0 : -5;
 }

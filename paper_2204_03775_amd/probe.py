@@ -5,7 +5,9 @@ the copy (1 read + 1 write) and read3-write1 (the propagator's per-update
 access mix) bandwidth in GB/s, for arrays of ``elements`` floats each
 (default: one 512^3 field in the propagator's padded layout).
 ``measure_sync`` gives the cost of synchronising work-groups inside one
-launch, against that of a launch.
+launch, against that of a launch; ``measure_step_stream`` the bandwidth of
+the step's own access pattern (tiles, z-chunks, in-place write) without its
+arithmetic, with every launch marching up and with alternating directions.
 """
 from __future__ import annotations
 
@@ -36,7 +38,60 @@ def _load():
     lib.probe_sync.restype = ci
     lib.probe_empty.argtypes = [ci, vp]
     lib.probe_empty.restype = ci
+    lib.probe_step_stream.argtypes = [vp, vp, vp, ci, ci, ci, i64, i64, ci, ci, vp]
+    lib.probe_step_stream.restype = ci
     return lib
+
+
+def measure_step_stream(nx: int = 512, ny: int = 512, nz: int = 512, zc: int = 256, launches: int = 20) -> dict:
+    """GB/s (16 bytes per interior cell) of the step's access pattern without
+    its arithmetic: a sequence of launches that swap the two wave fields, as
+    the propagator's run does, all marching z upwards, and alternating
+    direction launch by launch (what the library's tiled launches do).  Three
+    fields in the library's FP32 padded layout, 256 x 8 tiles, z-chunks of
+    zc planes."""
+    lib = _load()
+    x0 = 32
+    pitch = -(-(x0 + nx + 4) // 32) * 32
+    elems = pitch * (ny + 8) * (nz + 8)
+    f = [torch.rand(elems, device="cuda") for _ in range(3)]
+    stream = torch.cuda.current_stream()
+    s = stream.cuda_stream
+
+    def launch(a, b, down):
+        rc = lib.probe_step_stream(a.data_ptr(), b.data_ptr(), f[2].data_ptr(), nx, ny, nz, pitch, x0, zc,
+                                   int(down), s)
+        if rc != 0:
+            raise RuntimeError(f"probe_step_stream failed (code {rc})")
+
+    # one launch checked against its definition: b = a (four planes on) + b + k
+    view = lambda t: t.view(nz + 8, ny + 8, pitch)[:, 4:4 + ny, x0:x0 + nx]
+    b0 = view(f[1]).clone()
+    launch(f[0], f[1], False)
+    torch.cuda.synchronize()
+    ref = view(f[0])[8:8 + nz] + b0[4:4 + nz] + view(f[2])[4:4 + nz]
+    if not torch.equal(view(f[1])[4:4 + nz], ref):
+        raise RuntimeError("step-stream probe computed a wrong result")
+    del b0, ref
+    out = {"nx": nx, "ny": ny, "nz": nz, "zchunk": zc, "launches": launches}
+    for name, alternate in (("ascending", False), ("alternating", True)):
+        def seq(count):
+            a, b = f[0], f[1]
+            for i in range(count):
+                launch(a, b, alternate and (i & 1))
+                a, b = b, a
+        seq(4)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        seq(launches)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / launches
+        out[f"{name}_gbs"] = round(16.0 * nx * ny * nz / sec / 1e9, 1)
+        out[f"{name}_us"] = round(sec * 1e6, 2)
+    del f
+    return out
 
 
 def measure_sync(nsteps: int = 2000) -> dict:
