@@ -591,8 +591,11 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
             // next plane (clamped on the last one, whose loads go unused)
             prefetch(min(l + 1, len - 1), (s + 9) % QS, cur_set ^ 1);
             // imaging modes: this plane's accumulator values, loaded before
-            // the arithmetic so that their latency overlaps it; each cell is
-            // read and written once per step, so both are streamed
+            // the arithmetic so that their latency overlaps it.  Each cell is
+            // read and written once per step, but with the z-march reversed
+            // every launch the planes a launch touches last are the first
+            // the next one touches, so the accumulator keeps the default
+            // cache policy and the memory-side cache serves part of it
             dv2 gacc[GRAD ? RY : 1][2] = {};
             if constexpr (GRAD) {
 #pragma unroll
@@ -600,8 +603,8 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
                     if (col_full && row_int[r]) {
                         const dv2 *gp = reinterpret_cast<const dv2 *>(
                             a.grad + (long long)(z + kGhost) * a.plane + own_in[r] / EB);
-                        gacc[r][0] = __builtin_nontemporal_load(gp);
-                        gacc[r][1] = __builtin_nontemporal_load(gp + 1);
+                        gacc[r][0] = gp[0];
+                        gacc[r][1] = gp[1];
                     }
             }
 
@@ -772,8 +775,8 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
                             g0.y += (double)t.v[1];
                             g1.x += (double)t.v[2];
                             g1.y += (double)t.v[3];
-                            __builtin_nontemporal_store(g0, gp);
-                            __builtin_nontemporal_store(g1, gp + 1);
+                            gp[0] = g0;
+                            gp[1] = g1;
                         }
                     } else if (row_int[r]) {
                         double *gp = a.grad + (long long)(z + kGhost) * a.plane + own_in[r] / EB;
