@@ -1,10 +1,13 @@
-// F32-storage step kernels: the tiled kernel for every tile shape, the naive
-// kernel and its receiver sampler.
+// F32-storage step kernels: the tiled kernel for every tile shape (streaming
+// and cache-resident load policies), the naive kernel and its receiver
+// sampler.
 #include "wave_step.h"
 
 namespace wavek {
 
-#define INST(TXV, TY, RY) template __global__ void step_tiled<WAVE_F32, TXV, TY, RY>(StepArgs);
+#define INST(TXV, TY, RY)                                                  \
+    template __global__ void step_tiled<WAVE_F32, TXV, TY, RY>(StepArgs); \
+    template __global__ void step_tiled_cached<TXV, TY, RY>(StepArgs);
 WAVE_TILE_SHAPES(INST)
 #undef INST
 template __global__ void step_naive<WAVE_F32>(StepArgs);

@@ -78,6 +78,7 @@ struct Variant {
     RunKernel run[3];          // the same, every step of a run in one launch
     StepKernel adj[3];  // adjoint step, imaging step, fused adjoint + imaging (FP32)
     FlowKernel flow;    // data-flow batched step (FP32)
+    StepKernel fwd_cached;  // FP32 step with cache-resident load policies
     int txv, ty, ry;
 };
 
@@ -90,13 +91,13 @@ struct Variant {
     {step_batch_run<WAVE_F32, TXV, TY, RY>, step_batch_run<WAVE_F16, TXV, TY, RY>,                \
      step_batch_run<WAVE_BF16, TXV, TY, RY>},                                                     \
     {adjoint_tiled<kAdj, TXV, TY, RY>, adjoint_tiled<kImg, TXV, TY, RY>, adjoint_tiled<kFus, TXV, TY, RY>}, \
-    step_flow<TXV, TY, RY>
+    step_flow<TXV, TY, RY>, step_tiled_cached<TXV, TY, RY>
 
 const Variant kVariants[] = {
     {"auto", {nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr},
-     {nullptr, nullptr, nullptr}, nullptr, 0, 0, 0},
+     {nullptr, nullptr, nullptr}, nullptr, nullptr, 0, 0, 0},
     {"naive", {nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr},
-     {nullptr, nullptr, nullptr}, nullptr, 0, 0, 0},
+     {nullptr, nullptr, nullptr}, nullptr, nullptr, 0, 0, 0},
     {"t64x16_r1", TILED(16, 16, 1), 16, 16, 1},
     {"t128x8_r1", TILED(32, 8, 1), 32, 8, 1},
     {"t128x16_r2", TILED(32, 8, 2), 32, 8, 2},
@@ -115,6 +116,19 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kNaive = 1;
 const StepKernel kNaiveFn[kNumKinds] = {step_naive<WAVE_F32>, step_naive<WAVE_F16>, step_naive<WAVE_BF16>,
                                         step_naive<WAVE_F16_UV>, step_naive<WAVE_BF16_UV>};
+
+// Whether the cells an FP32 step touches in its three fields (u^n, u^{n-1},
+// k: the interior and 4 ghost rows and planes on each side) fit in the
+// GPU's 256 MiB memory-side cache with room to spare.  Then every field
+// keeps the default cache policy (step_tiled_cached): u^{n-1} and k, read
+// once per step, are still cached when the next step reads them.  Measured
+// with the step's access pattern: 13 % faster at 256^3 (about 210 MiB),
+// 8-13 % slower at 384^3, where streaming them is better.
+constexpr long long kCacheResidentBytes = 224ll << 20;
+bool fits_in_cache(int nx, int ny, int nz)
+{
+    return 3ll * 4 * (nx + 8) * (ny + 8) * (long long)(nz + 8) <= kCacheResidentBytes;
+}
 
 // The element encoding of a storage type (the u-and-change types store
 // both of their fields in the encoding of their base type).
@@ -166,6 +180,7 @@ struct wave_ctx {
     void *cur = nullptr, *prev = nullptr;
     int64_t step = 0;
     unsigned zflip = 0;  // tiled launches so far: their z-march directions alternate
+    bool cache_resident = false;  // FP32 fields small enough to stay in the memory-side cache
     int src[3] = {-1, -1, -1};
     std::vector<int32_t> rec;  // [nrec][3]
     int nrec = 0;
@@ -535,7 +550,8 @@ int enqueue_forward(wave_ctx *c, void *cur, void *prev, void *out, const float *
         }
     } else {
         const Variant &V = kVariants[c->v_used];
-        hipLaunchKernelGGL(V.fn[kind], dim3(c->grid), dim3(V.txv * V.ty), 0, c->stream, a);
+        const StepKernel fn = (c->cache_resident && V.fwd_cached) ? V.fwd_cached : V.fn[kind];
+        hipLaunchKernelGGL(fn, dim3(c->grid), dim3(V.txv * V.ty), 0, c->stream, a);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -1285,6 +1301,7 @@ int wave_init(wave_ctx **out, const wave_params_t *p, const void *k, void *u_cur
     c->p = *p;
     c->lay = lay;
     c->lay32 = lay32;
+    c->cache_resident = p->dtype == WAVE_F32 && fits_in_cache(p->nx, p->ny, p->nz);
     c->stream = static_cast<hipStream_t>(stream);
     c->k = k;
     c->buf0 = c->cur = u_cur;

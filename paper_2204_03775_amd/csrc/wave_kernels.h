@@ -10,6 +10,8 @@ namespace wavek {
 // kernels (defined in the k_*.hip translation units)
 template <int KIND, int TXV, int TY, int RY>
 __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a);
+template <int TXV, int TY, int RY>
+__global__ __launch_bounds__(TXV *TY) void step_tiled_cached(StepArgs a);
 template <int MODE, int TXV, int TY, int RY>
 __global__ __launch_bounds__(TXV *TY) void adjoint_tiled(StepArgs a);
 template <int KIND, int TXV, int TY, int RY>

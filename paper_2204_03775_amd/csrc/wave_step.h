@@ -354,7 +354,7 @@ __device__ __forceinline__ void static_for_while(F &&f)
 
 // One work-group's share of a step: the tile and z-chunk numbered `lid`
 // (tiles x fastest, then y, then chunks) of the grid described by `a`.
-template <int KIND, int TXV, int TY, int RY, int MODE = kFwd, bool COH = false>
+template <int KIND, int TXV, int TY, int RY, int MODE = kFwd, bool COH = false, bool CACHED = false>
 __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
 {
     constexpr int NT = TXV * TY;
@@ -372,9 +372,12 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
     constexpr bool IMG = MODE == kImg;
     constexpr bool GRAD = IMG || FUS;             // adds an imaging term to the FP64 accumulator
     static_assert(MODE == kFwd || KIND == WAVE_F32, "adjoint and imaging steps are FP32 only");
-    // load policies of the wave fields (k never changes during a run)
+    // load policies of the wave fields (k never changes during a run);
+    // CACHED: u^{n-1} and k too keep the default policy, for grids whose
+    // fields fit in the memory-side cache together
     constexpr int PK = kKeep | (COH ? kCoh : 0);
-    constexpr int PS = kStream | (COH ? kCoh : 0);
+    constexpr int PS = (CACHED ? kKeep : kStream) | (COH ? kCoh : 0);
+    constexpr int PKK = CACHED ? kKeep : kStream;
     __shared__ f4 lds[2][LH][LW];
     // second stencil field (the forward level of the imaging term), fused mode only
     __shared__ f4 lds2[FUS ? 2 : 1][FUS ? LH : 1][FUS ? LW : 1];
@@ -557,7 +560,7 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
         for (int r = 0; r < RY; ++r) {
             q[slot][r] = load4<KIND, PK>(rq, own_ld[r], 1.f);
             pv[set][r] = load_raw4<KIND, PS>(rp, own_in[r]);
-            kv[set][r] = load_raw4<KIND, kStream>(rk, own_in[r]);
+            kv[set][r] = load_raw4<KIND, PKK>(rk, own_in[r]);
         }
 #pragma unroll
         for (int h = 0; h < HPT; ++h)
@@ -843,6 +846,19 @@ __global__ __launch_bounds__(TXV *TY) void step_tiled(StepArgs a)
     if (lid >= a.nwg)
         return;
     tile_step<KIND, TXV, TY, RY>(a, lid);
+}
+
+// The FP32 step with every field read with the default cache policy: for
+// grids whose three fields fit in the GPU's memory-side cache together, so
+// that u^{n-1} and k, read once per step, are still cached at the next step
+// (the host picks it; same arithmetic as step_tiled).
+template <int TXV, int TY, int RY>
+__global__ __launch_bounds__(TXV *TY) void step_tiled_cached(StepArgs a)
+{
+    const int lid = logical_wg();
+    if (lid >= a.nwg)
+        return;
+    tile_step<WAVE_F32, TXV, TY, RY, kFwd, false, true>(a, lid);
 }
 
 template <int MODE, int TXV, int TY, int RY>
