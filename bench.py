@@ -362,21 +362,13 @@ def batched_leg(reps: int, single_launch: bool = True):
 
 
 def one_launch_run(props, shots, srcs, stream, choice, nt, reps, points, seq_traces, t_seq):
-    """The 32 shots in one launch: every shot with the same kernel (the one
-    the tuner chose for most cells, or the 128x16 tile), schedule 3."""
+    """The 32 shots in one launch (schedule 3): every shot with the same
+    kernel and z-chunk length, the pair timed fastest for that schedule."""
     import torch
 
-    from paper_2204_03775_amd import wave
+    from paper_2204_03775_amd import autotune, wave
 
-    names = {}
-    for p_, pr in zip(shots, props):
-        v, zc, _ = pr.config()
-        n = wave.wave_variant_name(v)
-        names[n] = names.get(n, 0) + p_.points
-    common = max(names, key=names.get) if choice["schedule"] != 1 else "t128x16_r1"
-    for pr in props:
-        _, zc, _ = pr.config()
-        pr.configure(common, zc)
+    common, zc = autotune.tune_one_launch(props, srcs, stream)
     b1 = wave.Batch(props, stream=stream, use_graph=False)
     b1.set_schedule(3)
     one_groups = b1.info()[0]
@@ -397,9 +389,9 @@ def one_launch_run(props, shots, srcs, stream, choice, nt, reps, points, seq_tra
     t_one = (time.perf_counter() - t0) / reps
     equal1 = all(torch.equal(a, pr.traces) for a, pr in zip(seq_traces, props))
     b1.close()
-    log(f"batched in one launch ({common}, {one_groups} group): {t_one * 1e3:.1f} ms "
+    log(f"batched in one launch ({common}, z-chunk {zc or 'whole depth'}, {one_groups} group): {t_one * 1e3:.1f} ms "
         f"({32 / t_one:.1f} shots/s, {points * nt / t_one / 1e9:.1f} Gpts/s); traces equal: {equal1}")
-    return {"schedule": 3, "kernel": common, "launch_groups": one_groups,
+    return {"schedule": 3, "kernel": common, "zchunk": zc or "whole depth", "launch_groups": one_groups,
             "ms": round(t_one * 1e3, 2), "shots_per_s": round(32 / t_one, 3),
             "gpts_per_s": round(points * nt / t_one / 1e9, 3),
             "speedup_vs_sequential": round(t_seq / t_one, 3),

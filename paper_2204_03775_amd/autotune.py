@@ -14,7 +14,9 @@ z-chunk fraction, timed on the batch itself one class at a time
 best for a shot alone is not best when all shots share each launch.
 Schedule 1 launches every shot with its own tuned configuration, spread
 over a few streams and replayed from one graph per stream.  The fastest is
-kept (schedule 3 only on request: see ``tune_batch``).
+kept (schedule 3 only on request: see ``tune_batch``).  ``tune_one_launch``
+picks the common kernel and z-chunk for running a whole batch as a single
+cooperative launch.
 
 Results are cached in a JSON file keyed by (GPU architecture, storage type,
 class); ``WAVE_TUNE_CACHE`` overrides its location.
@@ -210,6 +212,31 @@ def tune_batch(props, srcs, stream, nsteps: int = 30, use_cache: bool = True, lo
     apply(props, classes)
     return {"schedule": 3 if t_run < t_queue else 0, "nstreams": 1,
             "classes": {k: list(v) for k, v in classes.items()}, "us_per_step": times}
+
+
+ONE_LAUNCH_CHUNKS = (32, 64, 0)  # z-chunk planes (0: the whole grid depth)
+
+
+def tune_one_launch(props, srcs, stream, nsteps: int = 30, log=None) -> tuple:
+    """The fastest common (variant, z-chunk planes) for running the whole
+    batch as one cooperative launch (schedule 3: every shot must use the
+    same kernel to share the launch), timed with schedule 3 itself; leaves
+    the Propagators configured with it.  Call it after any multi-stream
+    replays the process still wants to time: see tune_batch."""
+    best = None
+    for name in VARIANTS:
+        for zc in ONE_LAUNCH_CHUNKS:
+            for p in props:
+                p.configure(name, zc if zc else p.nz)
+            t = time_batch(props, srcs, nsteps, stream, schedule=3)
+            if log:
+                log(f"tune one launch: {name} zc {zc or 'nz'}: {t * 1e6:.1f} us/step")
+            if best is None or t < best[0]:
+                best = (t, name, zc)
+    _, name, zc = best
+    for p in props:
+        p.configure(name, zc if zc else p.nz)
+    return name, zc
 
 
 def tune_classes(props, srcs, stream, nsteps: int = 30, use_cache: bool = True, log=None) -> dict:
