@@ -341,6 +341,39 @@ def test_single_launch_schedule_one_group_and_failure_path(wave_mod):
         pr.close()
 
 
+def test_one_launch_tuner_choice(wave_mod):
+    # tune_one_launch leaves every shot with the same kernel from its
+    # candidates (so the batch is one launch group), and the single-launch
+    # run with that choice is bit for bit the shots run alone with it
+    from paper_2204_03775_amd import autotune
+
+    shots = make_shots()
+    props, srcs = build(wave_mod, shots, "f32")
+    stream = torch.cuda.Stream()
+    print("case: tune_one_launch on the six test shots", flush=True)
+    name, zc = autotune.tune_one_launch(props, srcs, stream, nsteps=8)
+    assert name in autotune.VARIANTS and zc in autotune.ONE_LAUNCH_CHUNKS
+    assert {pr.config()[0] for pr in props} == {wave_mod.variants()[name]}
+    ref = []
+    for pr, s, p in zip(props, srcs, shots):
+        pr.reset()
+        pr.run(p.nt, s)
+        pr.sync()
+        ref.append(snapshot(pr))
+        pr.reset()
+    b = wave_mod.Batch(props, stream=stream, use_graph=False)
+    assert b.info()[0] == 1
+    b.set_schedule(3)
+    print(f"case: schedule 3 with the tuned {name}, z-chunk {zc}", flush=True)
+    b.run(shots[0].nt, srcs)
+    b.sync()
+    for i, pr in enumerate(props):
+        assert same(snapshot(pr), ref[i]), i
+    b.close()
+    for pr in props:
+        pr.close()
+
+
 def test_schedule_switch_and_bad_arguments(wave_mod):
     shots = make_shots()
     ref = alone(wave_mod, shots, "f32")
