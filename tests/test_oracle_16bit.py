@@ -12,6 +12,8 @@ bit.  It is pinned here against things outside itself:
   - every emulated step against the FP64 update of its own decoded inputs
     (the FP64 oracle's pointwise step), within the rounding the step's FP32
     arithmetic and 16-bit output allow;
+  - the headroom the level exponents leave: every stored maximum within
+    the range the exponent rule implies for this wave;
   - power-of-two equivariance of the level exponents: scaling the source by
     2^j leaves every stored bit unchanged and moves every exponent by j."""
 import numpy as np
@@ -98,6 +100,11 @@ def test_each_step_is_the_fp64_update_of_its_inputs(oracle_lib, prob, form):
     cur = _decode(oracle_lib, form, u1, e1[-1])
     if form.endswith("uv"):
         prev = cur - _decode(oracle_lib, form, d1, e1[-1] + 1)
+        # u^{n-1} rebuilt from u^n and the stored change is the level stored
+        # a step earlier, up to the rounding of the two stored values
+        ref_prev = _decode(oracle_lib, form, u0, e0[-1])
+        eps_f = 2.0 ** (-11 if form.startswith("f16") else -8)
+        assert np.abs(prev - ref_prev).max() <= 2 * eps_f * np.abs(ref_prev).max()
     else:
         prev = _decode(oracle_lib, form, u0, e0[-1])
     # k as the emulation stores it: one exponent ek with max k below 2^14 * 2^ek
@@ -119,13 +126,30 @@ def test_each_step_is_the_fp64_update_of_its_inputs(oracle_lib, prob, form):
     err = np.abs(got - ref)
     print(f"{form}: max |diff| {err.max():.3e} = {err.max() / (eps * M):.3f} eps M")
     assert err.max() <= 8 * eps * M
-    # the stored magnitudes stay below 2^14, and with the rule's factor 8 of
-    # headroom for the next level the largest one lands in [2^9, 2^11)
+    # the largest stored magnitude of the last level: the rule puts 8 M in
+    # [2^13, 2^14) stored units, and this wave's maximum changed little over
+    # the last steps, so it lies in [2^10, 2^11) (measured 1394..1400)
     raw = np.abs(_decode(oracle_lib, form, u2, 0))
-    assert 2.0 ** 9 <= raw.max() < 2.0 ** 11
+    assert 2.0 ** 10 <= raw.max() < 2.0 ** 11
     # the last trace row is the decoded u^{nt} at the receivers
     rz, ry, rx = np.asarray(p.rec).T
     assert np.array_equal(tr[-1], got.reshape(p.shape)[rz, ry, rx].astype(np.float32))
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_level_exponents_leave_the_stated_headroom(oracle_lib, prob, form):
+    # the exponent of each level puts 8 max(M_n, M_{n-1}) + |s_n| in
+    # [2^13, 2^14) stored units; the levels of this wave change their maximum
+    # by less than a factor 2 from step to step, so every stored maximum from
+    # the second level on lies in [2^10, 2^13) (measured 1270..5056): an
+    # exponent one off either way moves them out
+    p = prob
+    kw = dict(s=p.s.astype(np.float32), src=p.src, rec=p.rec, sponge_width=p.sponge_width,
+              sponge_alpha=p.sponge_alpha)
+    for n in range(2, p.nt + 1):
+        u, _, _, _ = oracle_lib.run16(p.k32(), p.h, n, form, **kw)
+        raw = np.abs(_decode(oracle_lib, form, u, 0)).max()
+        assert 2.0 ** 10 <= raw < 2.0 ** 13, (n, raw)
 
 
 @pytest.mark.parametrize("form", FORMS)
