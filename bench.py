@@ -33,7 +33,8 @@ HBM before timing starts.  The JSON line on stdout carries:
              update) or u and its step change (10 bytes): throughput,
              speedup over FP32 and HBM fraction, and the accuracy of every
              storage type against the FP64 oracle on a 128^3 crop of the
-             same model (500 steps);
+             same model (500 steps) and, with the CPU leg, over the whole
+             timed shot (against the oracle's whole run);
   batched    32 uneven shots (96..320 x 96..320 x 96..256, 600 steps each,
              FP32) as one autotuned batch replayed from a HIP graph (the
              tuner picks the schedule: one persistent launch per step, or
@@ -107,11 +108,12 @@ def measured_traffic(kernel_name: str, zchunk: int):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(p, max_steps: int = 0, gpu_final=None):
+def cpu_baseline(p, max_steps: int = 0, gpu_final=None, other_finals=None):
     """The FP64 oracle, as it stands, on the host cores: the whole shot (or
     its first max_steps steps), run in segments with a progress line after
     each.  When the whole shot ran and the GPU's final field and traces are
-    given, their relative L2 error against it is returned too."""
+    given, their relative L2 error against it is returned too, and likewise
+    for other_finals ({name: (field, traces)}, the 16-bit storage forms)."""
     import oracle
 
     threads = oracle.default_threads()
@@ -129,11 +131,18 @@ def cpu_baseline(p, max_steps: int = 0, gpu_final=None):
             "sample": f"{what} {p.nt}-step {p.nx}x{p.ny}x{p.nz} shot, FP64, {sec:.1f} s, "
                       f"OpenMP threads={threads} (nproc {os.cpu_count()}), cpu={_cpu_model()}"}
     acc = None
-    if gpu_final is not None and n == p.nt:
-        acc = {"rel_l2_field": rel_l2(gpu_final[0], cur), "rel_l2_traces": rel_l2(gpu_final[1], tr),
-               "workload": f"the whole {p.nx}x{p.ny}x{p.nz} x {p.nt}-step shot",
-               "reference": "FP64 oracle"}
-    return base, acc
+    others = {}
+    if n == p.nt:
+        def against(final):
+            return {"rel_l2_field": rel_l2(final[0], cur), "rel_l2_traces": rel_l2(final[1], tr),
+                    "workload": f"the whole {p.nx}x{p.ny}x{p.nz} x {p.nt}-step shot",
+                    "reference": "FP64 oracle"}
+
+        if gpu_final is not None:
+            acc = against(gpu_final)
+        for name, final in (other_finals or {}).items():
+            others[name] = against(final)
+    return base, acc, others
 
 
 def cpu_small_shot():
@@ -750,6 +759,7 @@ def main() -> int:
         f"{metrics.paper_tflops(gpts):.1f} TFLOP/s")
 
     forms = None
+    form_finals = {}
     crop_out = grad_crop_out = None
     if not args.no_forms and args.workload == "large_shot":
         prop.close()
@@ -765,6 +775,9 @@ def main() -> int:
             if not result_ok(pr):
                 log(f"error: non-finite or empty {dt} result")
                 return 1
+            if not args.no_cpu_baseline and not args.cpu_steps:
+                # the last timed shot's output, for the whole-shot comparison in the CPU leg
+                form_finals[dt] = (pr.export(0).cpu().numpy(), pr.traces[:, :pr.nrec].cpu().numpy())
             pr.close()
             g16 = metrics.gpts_per_s(p.nx, p.ny, p.nz, p.nt * args.steps, w16)
             a16 = bpp * p.points / k16 / 1e9
@@ -817,8 +830,16 @@ def main() -> int:
     cpu = None
     accuracy = None
     if not args.no_cpu_baseline:
-        cpu, accuracy = cpu_baseline(p, args.cpu_steps, gpu_final)
+        cpu, accuracy, form_acc = cpu_baseline(p, args.cpu_steps, gpu_final, form_finals)
         del gpu_final
+        form_finals.clear()
+        for dt, a in form_acc.items():
+            bound = ACCURACY_BOUNDS[dt]
+            a["bound"] = bound
+            a["meets_bound"] = bool(a["rel_l2_field"] <= bound and a["rel_l2_traces"] <= bound)
+            forms[dt]["accuracy_large_shot"] = a
+            log(f"{dt} accuracy over the whole shot: field {a['rel_l2_field']:.3e} traces "
+                f"{a['rel_l2_traces']:.3e} (bound {bound:g}: {'met' if a['meets_bound'] else 'NOT met'})")
         log(f"oracle: {cpu['value']} Gpts/s ({cpu['sample']})")
         if accuracy:
             log(f"FP32 accuracy over the whole shot: field {accuracy['rel_l2_field']:.3e} "
