@@ -98,6 +98,15 @@ struct Store<WAVE_F16> {
     {
         return __builtin_bit_cast(unsigned short, (_Float16)x);
     }
+    // two values packed low, high: one packed conversion (round to nearest
+    // even, as the scalar one) instead of two
+    static __device__ __forceinline__ unsigned enc2(float lo, float hi)
+    {
+        typedef float f2v __attribute__((ext_vector_type(2)));
+        typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+        const f2v f = {lo, hi};
+        return __builtin_bit_cast(unsigned, __builtin_convertvector(f, h2v));
+    }
 };
 template <>
 struct Store<WAVE_BF16> {
@@ -109,6 +118,7 @@ struct Store<WAVE_BF16> {
     {
         return __builtin_bit_cast(unsigned short, (__bf16)x);
     }
+    static __device__ __forceinline__ unsigned enc2(float lo, float hi) { return enc(lo) | (enc(hi) << 16); }
 };
 // u and its step change d = u^n - u^{n-1}, same 16-bit encodings
 template <>
@@ -210,7 +220,7 @@ __device__ __forceinline__ void store4(__amdgpu_buffer_rsrc_t r, unsigned off, c
         u2raw w;
 #pragma unroll
         for (int h = 0; h < 2; ++h)
-            w[h] = Store<KIND>::enc(v.v[2 * h] * inv) | (Store<KIND>::enc(v.v[2 * h + 1] * inv) << 16);
+            w[h] = Store<KIND>::enc2(v.v[2 * h] * inv, v.v[2 * h + 1] * inv);
         __builtin_amdgcn_raw_buffer_store_b64(w, r, off, 0, kStream);
     }
 }
