@@ -2,7 +2,9 @@
 
   python -m paper_2204_03775_amd.profile_summary stats DIR/PREFIX --command CMD --out FILE.md
       kernel-trace statistics (<prefix>_kernel_stats.csv): the kernels by
-      total time, with calls and average duration;
+      total time, with calls and average duration, and, where the kernel
+      trace (<prefix>_kernel_trace.csv) is beside it, each kernel's registers,
+      LDS and the occupancy they allow;
 
   python -m paper_2204_03775_amd.profile_summary kernels --fetch F --write W \\
       --fetch-probe PF --write-probe PW --title T --commands CMDS --out FILE.md
@@ -81,6 +83,56 @@ def pick(d, key):
     return hits[0]
 
 
+# gfx950 compute unit: 4 SIMDs, at most 8 waves each, 512 vector registers
+# per lane in each SIMD (architectural and accumulation registers share them),
+# 160 KiB of LDS
+SIMDS_PER_CU = 4
+MAX_WAVES_PER_SIMD = 8
+VGPRS_PER_SIMD_LANE = 512
+LDS_BYTES_PER_CU = 160 * 1024
+
+
+def occupancy(vgpr: int, agpr: int, lds: int, wg_size: int):
+    """(work-groups per CU, waves per SIMD) that the vector registers and the
+    LDS of one work-group allow.  ``vgpr`` and ``agpr`` are the allocated
+    counts per lane (as the kernel trace reports them), ``lds`` the bytes per
+    work-group.  Scalar registers are not counted."""
+    waves_wg = -(-wg_size // 64)
+    regs = vgpr + agpr
+    per_simd = MAX_WAVES_PER_SIMD if regs == 0 else min(MAX_WAVES_PER_SIMD, VGPRS_PER_SIMD_LANE // regs)
+    slots = SIMDS_PER_CU * per_simd  # waves a CU holds at this register count
+    wgs = slots // waves_wg
+    if lds > 0:
+        wgs = min(wgs, LDS_BYTES_PER_CU // lds)
+    return wgs, wgs * waves_wg / SIMDS_PER_CU
+
+
+def resources(trace_csv: str, names):
+    """Resource rows (registers, LDS, work-group size, occupancy) of the
+    kernels ``names``, from a kernel trace (the first dispatch of each)."""
+    first = {}
+    with open(trace_csv) as f:
+        for r in csv.DictReader(f):
+            if r["Kernel_Name"] in names and r["Kernel_Name"] not in first:
+                first[r["Kernel_Name"]] = r
+    lines = ["", "Resources (first dispatch of each kernel; occupancy from the vector registers and LDS",
+             "alone: 4 SIMDs per CU, at most 8 waves and 512 registers per lane each, 160 KiB of LDS):", "",
+             "| kernel | VGPR | AGPR | SGPR | LDS bytes | scratch | work-group | work-groups launched | "
+             "work-groups / CU | waves / SIMD |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for n in names:
+        r = first.get(n)
+        if r is None:
+            continue
+        v, acc, lds = int(r["VGPR_Count"]), int(r["Accum_VGPR_Count"]), int(r["LDS_Block_Size"])
+        wg = int(r["Workgroup_Size_X"]) * int(r["Workgroup_Size_Y"]) * int(r["Workgroup_Size_Z"])
+        grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        wgs, waves = occupancy(v, acc, lds, wg)
+        lines.append(f"| `{_short(n)}` | {v} | {acc} | {r['SGPR_Count']} | {lds} | {r['Scratch_Size']} | {wg} | "
+                     f"{-(-grid // wg)} | {wgs} | {waves:g} |")
+    return lines
+
+
 def stats(prefix: str, command: str, out: str):
     rows = list(csv.DictReader(open(prefix + "_kernel_stats.csv")))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
@@ -91,6 +143,8 @@ def stats(prefix: str, command: str, out: str):
         lines.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                      f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                      f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    if os.path.exists(prefix + "_kernel_trace.csv"):
+        lines += resources(prefix + "_kernel_trace.csv", [r["Name"] for r in rows[:12]])
     open(out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 

@@ -33,3 +33,17 @@ def test_overlap_counts_concurrent_time():
     assert (n, q, busy, span, multi) == (3, 2, 35, 30, 5)
     # back to back on one queue: no overlap
     assert ps.overlap_of(rows[:1] + rows[2:])[4] == 0
+
+
+def test_occupancy_from_registers_and_lds():
+    # 512 threads = 8 waves; 68 registers: 512 // 68 = 7 waves per SIMD,
+    # 28 wave slots per CU hold 3 work-groups; 33792 B of LDS allow 4
+    assert ps.occupancy(68, 0, 33792, 512) == (3, 6.0)
+    # 184 registers: 2 waves per SIMD, one 512-thread work-group per CU
+    assert ps.occupancy(184, 0, 0, 512) == (1, 2.0)
+    # the LDS binds: 4 work-groups by registers, 2 by 70 KiB of LDS
+    assert ps.occupancy(64, 0, 70 * 1024, 512) == (2, 4.0)
+    # accumulation registers come out of the same file: 256 in all, 2 waves per SIMD
+    assert ps.occupancy(128, 128, 0, 256) == (2, 2.0)
+    # no registers reported: the wave limit of 8 per SIMD
+    assert ps.occupancy(0, 0, 0, 64) == (32, 8.0)
