@@ -3,8 +3,8 @@
   python -m paper_2204_03775_amd.profile_summary stats DIR/PREFIX --command CMD --out FILE.md
       kernel-trace statistics (<prefix>_kernel_stats.csv): the kernels by
       total time, with calls and average duration, and, where the kernel
-      trace (<prefix>_kernel_trace.csv) is beside it, each kernel's registers,
-      LDS and the occupancy they allow;
+      trace and agent list (<prefix>_kernel_trace.csv, _agent_info.csv) are
+      beside it, each kernel's registers, LDS and the occupancy they allow;
 
   python -m paper_2204_03775_amd.profile_summary kernels --fetch F --write W \\
       --fetch-probe PF --write-probe PW --title T --commands CMDS --out FILE.md
@@ -107,16 +107,32 @@ def occupancy(vgpr: int, agpr: int, lds: int, wg_size: int):
     return wgs, wgs * waves_wg / SIMDS_PER_CU
 
 
-def resources(trace_csv: str, names):
+# GPUs whose kernels allocate vector registers in granules of 8 (one
+# 512-register file per SIMD lane).  The kernel trace prints the count
+# decoded with a granule of 4, half the allocation: the compiler's resource
+# report for the same kernels gives 130, 176 and 186 registers where the
+# trace prints 68, 88 and 96 (each rounded up to 8, then halved).
+GRANULE8_TARGETS = ("gfx90a", "gfx942", "gfx950")
+
+
+def allocated_vgprs(printed: int, target: str) -> int:
+    return 2 * printed if target in GRANULE8_TARGETS else printed
+
+
+def resources(trace_csv: str, names, target: str = ""):
     """Resource rows (registers, LDS, work-group size, occupancy) of the
-    kernels ``names``, from a kernel trace (the first dispatch of each)."""
+    kernels ``names``, from a kernel trace (the first dispatch of each) of a
+    GPU of ISA ``target``."""
     first = {}
     with open(trace_csv) as f:
         for r in csv.DictReader(f):
             if r["Kernel_Name"] in names and r["Kernel_Name"] not in first:
                 first[r["Kernel_Name"]] = r
-    lines = ["", "Resources (first dispatch of each kernel; occupancy from the vector registers and LDS",
-             "alone: 4 SIMDs per CU, at most 8 waves and 512 registers per lane each, 160 KiB of LDS):", "",
+    lines = ["", f"Resources on {target or 'the GPU'} (first dispatch of each kernel).  Vector registers as "
+             "allocated per lane",
+             "(twice the count the trace prints on this GPU, which decodes it with a granule of 4 instead of 8);",
+             "occupancy from the registers and LDS alone: 4 SIMDs per CU, at most 8 waves and 512 registers",
+             "per lane each, 160 KiB of LDS:", "",
              "| kernel | VGPR | AGPR | SGPR | LDS bytes | scratch | work-group | work-groups launched | "
              "work-groups / CU | waves / SIMD |",
              "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
@@ -124,13 +140,24 @@ def resources(trace_csv: str, names):
         r = first.get(n)
         if r is None:
             continue
-        v, acc, lds = int(r["VGPR_Count"]), int(r["Accum_VGPR_Count"]), int(r["LDS_Block_Size"])
+        v = allocated_vgprs(int(r["VGPR_Count"]), target)
+        acc = allocated_vgprs(int(r["Accum_VGPR_Count"]), target)
+        lds = int(r["LDS_Block_Size"])
         wg = int(r["Workgroup_Size_X"]) * int(r["Workgroup_Size_Y"]) * int(r["Workgroup_Size_Z"])
         grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
         wgs, waves = occupancy(v, acc, lds, wg)
         lines.append(f"| `{_short(n)}` | {v} | {acc} | {r['SGPR_Count']} | {lds} | {r['Scratch_Size']} | {wg} | "
                      f"{-(-grid // wg)} | {wgs} | {waves:g} |")
     return lines
+
+
+def gpu_target(agent_csv: str) -> str:
+    """ISA name of the first GPU agent in an agent-info file."""
+    with open(agent_csv) as f:
+        for r in csv.DictReader(f):
+            if r["Name"].startswith("gfx"):
+                return r["Name"]
+    return ""
 
 
 def stats(prefix: str, command: str, out: str):
@@ -143,8 +170,9 @@ def stats(prefix: str, command: str, out: str):
         lines.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                      f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                      f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
-    if os.path.exists(prefix + "_kernel_trace.csv"):
-        lines += resources(prefix + "_kernel_trace.csv", [r["Name"] for r in rows[:12]])
+    if os.path.exists(prefix + "_kernel_trace.csv") and os.path.exists(prefix + "_agent_info.csv"):
+        lines += resources(prefix + "_kernel_trace.csv", [r["Name"] for r in rows[:12]],
+                           gpu_target(prefix + "_agent_info.csv"))
     open(out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 

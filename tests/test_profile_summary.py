@@ -47,3 +47,10 @@ def test_occupancy_from_registers_and_lds():
     assert ps.occupancy(128, 128, 0, 256) == (2, 2.0)
     # no registers reported: the wave limit of 8 per SIMD
     assert ps.occupancy(0, 0, 0, 64) == (32, 8.0)
+
+
+def test_trace_register_counts_are_doubled_on_granule_8_gpus():
+    # what the trace printed for three kernels whose allocation the compiler
+    # reports as 130, 176 and 186 registers (136, 176 and 192 allocated)
+    assert [ps.allocated_vgprs(n, "gfx950") for n in (68, 88, 96)] == [136, 176, 192]
+    assert ps.allocated_vgprs(68, "gfx1100") == 68
