@@ -1080,11 +1080,11 @@ int run_enqueue(wave_batch *b, int nsteps)
     return hipGetLastError() == hipSuccess ? WAVE_OK : WAVE_EHIP;
 }
 
-// Schedule 1: each shot's steps on one of the K streams with the shot's own kernel;
-// the contexts' bookkeeping advances as the launches are enqueued.
-// Schedule 1: the shots of each stream.  Largest shots first, each to the
-// stream with the least work so far (work = cells per step), so the streams
-// end close together.
+// Schedule 1: each shot's steps on one of the K streams with the shot's own
+// kernel; the contexts' bookkeeping advances as the launches are enqueued.
+// The shots of each stream: largest shots first, each to the stream with
+// the least work so far (work = cells per step), so the streams end close
+// together.
 std::vector<std::vector<size_t>> stream_shots(const wave_batch *b)
 {
     const size_t K = b->aux.size();
