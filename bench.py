@@ -31,7 +31,9 @@ HBM before timing starts.  The JSON line on stdout carries:
   forms      the 16-bit storage forms (FP32 arithmetic) on the same shot:
              FP16 and BF16 holding two time levels (8 algorithmic bytes per
              update) or u and its step change (10 bytes): throughput,
-             speedup over FP32 and HBM fraction, and the accuracy of every
+             speedup over FP32 and HBM fraction (also against the
+             bandwidth of the form's own access pattern streamed without
+             arithmetic, with its tiles and z-chunks), and the accuracy of every
              storage type against the FP64 oracle on a 128^3 crop of the
              same model (500 steps) and, with the CPU leg, over the whole
              timed shot (against the oracle's whole run);
@@ -171,6 +173,24 @@ def cpu_small_shot():
 # reduced-precision storage (FP16 5e-3, BF16 5e-2).  The two-level forms
 # are reported against them as measured, met or not.
 ACCURACY_BOUNDS = {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2, "f16uv": 5e-3, "bf16uv": 5e-2}
+
+
+def step_stream16(p, kernel: str, zchunk: int, uv: bool):
+    """The 16-bit step-stream probe with the form's tiles and z-chunk (None
+    for a tiling the probe does not cover or without the probe library)."""
+    import re
+
+    m = re.fullmatch(r"t(\d+)x(\d+)_r(\d+)", kernel)
+    if not m or int(m.group(1)) != 128:
+        return None
+    rows, ry = int(m.group(2)), int(m.group(3))
+    if rows % ry or (rows // ry, ry) not in ((8, 1), (8, 2), (16, 1), (16, 2), (32, 1)):
+        return None
+    try:
+        from paper_2204_03775_amd import probe
+    except ImportError:
+        return None
+    return probe.measure_step_stream16(p.nx, p.ny, p.nz, zchunk, rows // ry, ry, uv)
 
 
 def rel_l2(a, b) -> float:
@@ -781,14 +801,21 @@ def main() -> int:
             pr.close()
             g16 = metrics.gpts_per_s(p.nx, p.ny, p.nz, p.nt * args.steps, w16)
             a16 = bpp * p.points / k16 / 1e9
+            kname16 = wave.wave_variant_name(v16)
+            stream16 = step_stream16(p, kname16, zc16, dt.endswith("uv"))
             forms[dt] = {"value": round(g16, 3), "unit": "Gpts/s", "speedup_vs_f32": round(g16 / gpts, 3),
-                         "kernel": wave.wave_variant_name(v16), "zchunk": zc16,
+                         "kernel": kname16, "zchunk": zc16,
                          "roofline": {"bound": "hbm", "achieved": round(a16, 1),
                                       "peak": metrics.MI355X_HBM_PEAK_GBS, "unit": "GB/s",
                                       "frac": round(a16 / metrics.MI355X_HBM_PEAK_GBS, 4),
-                                      "bytes_per_point": bpp}}
+                                      "bytes_per_point": bpp,
+                                      "step_stream_measured": stream16,
+                                      "frac_of_step_stream": (round(a16 / stream16["alternating_gbs"], 4)
+                                                              if stream16 else None)}}
             log(f"{dt}: {g16:.1f} Gpts/s ({g16 / gpts:.2f}x FP32), kernel {k16 * 1e6:.1f} us = "
-                f"{a16:.0f} GB/s at {bpp} B/pt")
+                f"{a16:.0f} GB/s at {bpp} B/pt"
+                + (f"; its access pattern alone streams {stream16['alternating_gbs']:.0f} GB/s"
+                   if stream16 else ""))
         crop_out = crop_runs()
 
     batched = None

@@ -60,6 +60,20 @@ int probe_empty(int blocks, void *stream);
 int probe_step_stream(const float *a, float *b, const float *k, int nx, int ny, int nz, int64_t pitch,
                       int64_t x0, int zc, int down, void *stream);
 
+/* The same for the 16-bit storage forms: 2-byte cells, fields of nz + 8
+ * planes of ny + 8 rows of `pitch` cells with interior x from cell x0 (nx,
+ * x0, pitch multiples of 4; 8-byte aligned pointers).  Tiles of 32 x ty
+ * threads, each thread 4 cells in ry rows ((ty, ry) one of (8, 1), (8, 2),
+ * (16, 1), (16, 2), (32, 1): the 16-bit step kernels' tiles of 128 cells),
+ * z-chunks of zc planes.  o == NULL: the two-level step's pattern, u read
+ * four planes ahead of the march and p, k at the plane, p = u ^ p ^ k
+ * written in place (8 bytes per cell).  o != NULL: the u-and-change step's
+ * pattern, u ahead and p (the change), k at the plane, o = u ^ k written to
+ * o and p = p ^ u in place (10 bytes per cell).  Cache policies are the
+ * step kernels': u default, the rest non-temporal.  -1 for bad arguments. */
+int probe_step_stream16(const void *u, void *p, void *o, const void *k, int nx, int ny, int nz, int64_t pitch,
+                        int64_t x0, int zc, int ty, int ry, int down, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

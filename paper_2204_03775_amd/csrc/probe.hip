@@ -233,6 +233,85 @@ __global__ __launch_bounds__(512) void step_stream_k(const f4 *__restrict__ a, f
     }
 }
 
+// The same for the 16-bit storage forms (2-byte cells; a padded field has
+// nz + 8 planes of ny + 8 rows of `pitch` cells, interior x from cell x0).
+// Tiles of 32 x TY threads, each thread 4 consecutive cells (8 bytes) in RY
+// rows, and z-chunks of zc planes, as the 16-bit step kernels tile a grid.
+// Two levels (UV false): read u four planes ahead of the march (default
+// policy) and p, k at the plane (non-temporal), write p = u ^ p ^ k in place
+// (non-temporal): 8 bytes per cell.  u and step change (UV true): read u
+// ahead, d and k at the plane, write o = u ^ k into the other level buffer
+// and d = d ^ u in place: 10 bytes per cell.  Bitwise XOR keeps the check
+// exact for any bit pattern.  Out-of-range cells get an offset past the
+// plane's buffer resource, so they read zero and store nothing.
+typedef unsigned u2raw __attribute__((vector_size(8)));
+constexpr int kRawWord3 = 0x00020000;  // raw (stride 0) 32-bit buffer access
+constexpr int kPolKeep = 0, kPolStream = 2;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane16(const void *f, long long plane_bytes, int z)
+{
+    const char *p = reinterpret_cast<const char *>(f) + (long long)(z + 4) * plane_bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), (short)0, (int)plane_bytes, kRawWord3);
+}
+
+template <int TY, int RY, bool UV>
+__global__ __launch_bounds__(32 * TY) void step_stream16_k(const void *u, void *p, void *o, const void *k,
+                                                           int nxq, int ny, int nz, long long pitch,
+                                                           long long plane_bytes, int x0, int zc, int ntx,
+                                                           int nty, int nwg, int down)
+{
+    const int per = gridDim.x >> 3;
+    const int lid = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (lid >= nwg)
+        return;
+    const int tx = lid % ntx, rest = lid / ntx, ty = rest % nty, ch = rest / nty;
+    const int z0 = ch * zc, z1 = min(z0 + zc, nz), len = z1 - z0;
+    const int q = tx * 32 + (int)(threadIdx.x % 32);
+    const int r0 = (ty * TY + (int)(threadIdx.x / 32)) * RY;
+    unsigned off[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+        off[r] = (q < nxq && r0 + r < ny) ? 2u * unsigned((r0 + r + 4) * pitch + x0 + 4 * q) : 0xffffffffu;
+    const int dz = down ? -1 : 1;
+    const int zs = down ? z1 - 1 : z0;
+    u2raw un[RY], pn[RY], kn[RY];
+    auto load = [&](int z) {
+        const __amdgpu_buffer_rsrc_t ru = plane16(u, plane_bytes, z + 4 * dz);
+        const __amdgpu_buffer_rsrc_t rp = plane16(p, plane_bytes, z);
+        const __amdgpu_buffer_rsrc_t rk = plane16(k, plane_bytes, z);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            un[r] = __builtin_amdgcn_raw_buffer_load_b64(ru, off[r], 0, kPolKeep);
+            pn[r] = __builtin_amdgcn_raw_buffer_load_b64(rp, off[r], 0, kPolStream);
+            kn[r] = __builtin_amdgcn_raw_buffer_load_b64(rk, off[r], 0, kPolStream);
+        }
+    };
+    load(zs);
+    for (int l = 0; l < len; ++l) {
+        const int z = zs + l * dz;
+        u2raw a[RY], b[RY], c[RY];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            a[r] = un[r];
+            b[r] = pn[r];
+            c[r] = kn[r];
+        }
+        if (l + 1 < len)
+            load(z + dz);
+        const __amdgpu_buffer_rsrc_t rp = plane16(p, plane_bytes, z);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            if constexpr (UV) {
+                __builtin_amdgcn_raw_buffer_store_b64(a[r] ^ c[r], plane16(o, plane_bytes, z), off[r], 0,
+                                                      kPolStream);
+                __builtin_amdgcn_raw_buffer_store_b64(b[r] ^ a[r], rp, off[r], 0, kPolStream);
+            } else {
+                __builtin_amdgcn_raw_buffer_store_b64(a[r] ^ b[r] ^ c[r], rp, off[r], 0, kPolStream);
+            }
+        }
+    }
+}
+
 bool bad(const void *p) { return !p || (reinterpret_cast<uintptr_t>(p) & 15u); }
 
 int grid_for(long long n4)
@@ -319,4 +398,41 @@ extern "C" int probe_step_stream(const float *a, float *b, const float *k, int n
     hipLaunchKernelGGL(step_stream_k, dim3(grid), dim3(512), 0, (hipStream_t)stream, (const f4 *)a, (f4 *)b,
                        (const f4 *)k, nx4, ny, nz, pitch4, plane4, int(x0 / 4), zc, ntx, nty, int(nwg), down ? 1 : 0);
     return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
+extern "C" int probe_step_stream16(const void *u, void *p, void *o, const void *k, int nx, int ny, int nz,
+                                   int64_t pitch, int64_t x0, int zc, int ty, int ry, int down, void *stream)
+{
+    auto bad8 = [](const void *q) { return !q || (reinterpret_cast<uintptr_t>(q) & 7u); };
+    if (bad8(u) || bad8(p) || bad8(k) || (o && bad8(o)) || nx < 4 || (nx & 3) || ny < 1 || nz < 1 || zc < 1 ||
+        (pitch & 3) || (x0 & 3) || x0 < 4 || pitch < x0 + nx + 4)
+        return -1;
+    const long long plane_bytes = (long long)pitch * (ny + 8) * 2;
+    if (plane_bytes >= (1ll << 31))
+        return -1;
+    const int nxq = nx / 4;
+    const int ntx = (nxq + 31) / 32, nty = (ny + ty * ry - 1) / (ty * ry), nch = (nz + zc - 1) / zc;
+    const long long nwg = (long long)ntx * nty * nch;
+    if (nwg > (1ll << 30))
+        return -1;
+    const int grid = int((nwg + 7) / 8 * 8);
+#define STREAM16(TY, RY)                                                                                     \
+    if (ty == TY && ry == RY) {                                                                              \
+        if (o)                                                                                               \
+            hipLaunchKernelGGL((step_stream16_k<TY, RY, true>), dim3(grid), dim3(32 * TY), 0,                \
+                               (hipStream_t)stream, u, p, o, k, nxq, ny, nz, (long long)pitch, plane_bytes,  \
+                               int(x0), zc, ntx, nty, int(nwg), down ? 1 : 0);                               \
+        else                                                                                                 \
+            hipLaunchKernelGGL((step_stream16_k<TY, RY, false>), dim3(grid), dim3(32 * TY), 0,               \
+                               (hipStream_t)stream, u, p, o, k, nxq, ny, nz, (long long)pitch, plane_bytes,  \
+                               int(x0), zc, ntx, nty, int(nwg), down ? 1 : 0);                               \
+        return hipGetLastError() == hipSuccess ? 0 : -5;                                                     \
+    }
+    STREAM16(8, 1)
+    STREAM16(8, 2)
+    STREAM16(16, 1)
+    STREAM16(16, 2)
+    STREAM16(32, 1)
+#undef STREAM16
+    return -1;
 }

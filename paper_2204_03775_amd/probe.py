@@ -7,7 +7,8 @@ access mix) bandwidth in GB/s, for arrays of ``elements`` floats each
 ``measure_sync`` gives the cost of synchronising work-groups inside one
 launch, against that of a launch; ``measure_step_stream`` the bandwidth of
 the step's own access pattern (tiles, z-chunks, in-place write) without its
-arithmetic, with every launch marching up and with alternating directions.
+arithmetic, with every launch marching up and with alternating directions,
+and ``measure_step_stream16`` the same for the 16-bit storage forms.
 """
 from __future__ import annotations
 
@@ -40,6 +41,8 @@ def _load():
     lib.probe_empty.restype = ci
     lib.probe_step_stream.argtypes = [vp, vp, vp, ci, ci, ci, i64, i64, ci, ci, vp]
     lib.probe_step_stream.restype = ci
+    lib.probe_step_stream16.argtypes = [vp, vp, vp, vp, ci, ci, ci, i64, i64, ci, ci, ci, ci, vp]
+    lib.probe_step_stream16.restype = ci
     return lib
 
 
@@ -89,6 +92,76 @@ def measure_step_stream(nx: int = 512, ny: int = 512, nz: int = 512, zc: int = 2
         torch.cuda.synchronize()
         sec = e0.elapsed_time(e1) / 1e3 / launches
         out[f"{name}_gbs"] = round(16.0 * nx * ny * nz / sec / 1e9, 1)
+        out[f"{name}_us"] = round(sec * 1e6, 2)
+    del f
+    return out
+
+
+def measure_step_stream16(nx: int, ny: int, nz: int, zc: int, ty: int, ry: int, uv: bool,
+                          launches: int = 20) -> dict:
+    """The same for a 16-bit storage form: GB/s at 8 bytes per interior
+    cell (two levels) or 10 (u and step change), of launches that swap the
+    level buffers, all marching up and alternating direction.  Tiles of 128
+    cells x ty * ry rows (32 x ty threads), z-chunks of zc planes, as the
+    form's step kernel tiles the grid."""
+    lib = _load()
+    x0 = 64  # 128-byte aligned interior rows
+    pitch = -(-(x0 + nx + 4) // 64) * 64
+    elems = pitch * (ny + 8) * (nz + 8)
+    nf = 4 if uv else 3
+    f = [torch.randint(-32768, 32767, (elems,), dtype=torch.int16, device="cuda") for _ in range(nf)]
+    stream = torch.cuda.current_stream()
+    s = stream.cuda_stream
+
+    def launch(u, p, o, down):
+        rc = lib.probe_step_stream16(u.data_ptr(), p.data_ptr(), o.data_ptr() if o is not None else None,
+                                     f[2].data_ptr(), nx, ny, nz, pitch, x0, zc, ty, ry, int(down), s)
+        if rc != 0:
+            raise RuntimeError(f"probe_step_stream16 failed (code {rc})")
+
+    # one launch checked against its definition, every cell of the written fields
+    view = lambda t: t.view(nz + 8, ny + 8, pitch)
+    inner = lambda t, dz=0: view(t)[4 + dz:4 + dz + nz, 4:4 + ny, x0:x0 + nx]
+    ahead = inner(f[0], 4)
+    if uv:
+        want_o, want_d = f[3].clone(), f[1].clone()
+        inner(want_o).copy_(ahead ^ inner(f[2]))
+        inner(want_d).copy_(inner(f[1]) ^ ahead)
+        launch(f[0], f[1], f[3], False)
+        torch.cuda.synchronize()
+        ok = torch.equal(f[3], want_o) and torch.equal(f[1], want_d)
+        del want_o, want_d
+    else:
+        want = f[1].clone()
+        inner(want).copy_(ahead ^ inner(f[1]) ^ inner(f[2]))
+        launch(f[0], f[1], None, False)
+        torch.cuda.synchronize()
+        ok = torch.equal(f[1], want)
+        del want
+    del ahead
+    if not ok:
+        raise RuntimeError("16-bit step-stream probe computed a wrong result")
+    bpp = 10 if uv else 8
+    out = {"form": "u and step change" if uv else "two levels", "bytes_per_point": bpp, "nx": nx, "ny": ny,
+           "nz": nz, "zchunk": zc, "tile": f"t128x{ty * ry}_r{ry}", "launches": launches}
+    for name, alternate in (("ascending", False), ("alternating", True)):
+        def seq(count):
+            a, b = f[0], (f[3] if uv else f[1])
+            for i in range(count):
+                if uv:
+                    launch(a, f[1], b, alternate and (i & 1))
+                else:
+                    launch(a, b, None, alternate and (i & 1))
+                a, b = b, a
+        seq(4)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        seq(launches)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / launches
+        out[f"{name}_gbs"] = round(bpp * nx * ny * nz / sec / 1e9, 1)
         out[f"{name}_us"] = round(sec * 1e6, 2)
     del f
     return out
