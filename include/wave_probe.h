@@ -70,7 +70,8 @@ int probe_step_stream(const float *a, float *b, const float *k, int nx, int ny, 
  * written in place (8 bytes per cell).  o != NULL: the u-and-change step's
  * pattern, u ahead and p (the change), k at the plane, o = u ^ k written to
  * o and p = p ^ u in place (10 bytes per cell).  Cache policies are the
- * step kernels': u default, the rest non-temporal.  -1 for bad arguments. */
+ * step kernels': u (and the change p) read with the default policy, the
+ * other accesses non-temporal.  -1 for bad arguments. */
 int probe_step_stream16(const void *u, void *p, void *o, const void *k, int nx, int ny, int nz, int64_t pitch,
                         int64_t x0, int zc, int ty, int ry, int down, void *stream);
 

@@ -240,8 +240,9 @@ __global__ __launch_bounds__(512) void step_stream_k(const f4 *__restrict__ a, f
 // Two levels (UV false): read u four planes ahead of the march (default
 // policy) and p, k at the plane (non-temporal), write p = u ^ p ^ k in place
 // (non-temporal): 8 bytes per cell.  u and step change (UV true): read u
-// ahead, d and k at the plane, write o = u ^ k into the other level buffer
-// and d = d ^ u in place: 10 bytes per cell.  Bitwise XOR keeps the check
+// ahead and d (default policy, as the step reads its change) and k at the
+// plane, write o = u ^ k into the other level buffer and d = d ^ u in place:
+// 10 bytes per cell.  Bitwise XOR keeps the check
 // exact for any bit pattern.  Out-of-range cells get an offset past the
 // plane's buffer resource, so they read zero and store nothing.
 typedef unsigned u2raw __attribute__((vector_size(8)));
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(32 * TY) void step_stream16_k(const void *u, void *
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             un[r] = __builtin_amdgcn_raw_buffer_load_b64(ru, off[r], 0, kPolKeep);
-            pn[r] = __builtin_amdgcn_raw_buffer_load_b64(rp, off[r], 0, kPolStream);
+            pn[r] = __builtin_amdgcn_raw_buffer_load_b64(rp, off[r], 0, UV ? kPolKeep : kPolStream);
             kn[r] = __builtin_amdgcn_raw_buffer_load_b64(rk, off[r], 0, kPolStream);
         }
     };

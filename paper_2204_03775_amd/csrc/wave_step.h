@@ -384,9 +384,14 @@ __device__ __forceinline__ void tile_step(const StepArgs &a, int lid)
     static_assert(MODE == kFwd || KIND == WAVE_F32, "adjoint and imaging steps are FP32 only");
     // load policies of the wave fields (k never changes during a run);
     // CACHED: u^{n-1} and k too keep the default policy, for grids whose
-    // fields fit in the memory-side cache together
+    // fields fit in the memory-side cache together.  The step change d^n of
+    // the u-and-change forms keeps it too: with the z-march reversed every
+    // launch, the d planes one launch touches last are the next one's first,
+    // and the memory-side cache serves part of them (512^3: FP16 513 -> 526,
+    // BF16 519 -> 546 Gpts/s; also keeping k was slower, and so was keeping
+    // u^{n-1} and k in the two-level forms)
     constexpr int PK = kKeep | (COH ? kCoh : 0);
-    constexpr int PS = (CACHED ? kKeep : kStream) | (COH ? kCoh : 0);
+    constexpr int PS = ((CACHED || UV) ? kKeep : kStream) | (COH ? kCoh : 0);
     constexpr int PKK = CACHED ? kKeep : kStream;
     __shared__ f4 lds[2][LH][LW];
     // second stencil field (the forward level of the imaging term), fused mode only
