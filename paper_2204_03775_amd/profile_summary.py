@@ -141,7 +141,8 @@ def resources(trace_csv: str, names, target: str = ""):
         if r is None:
             continue
         v = allocated_vgprs(int(r["VGPR_Count"]), target)
-        acc = allocated_vgprs(int(r["Accum_VGPR_Count"]), target)
+        # accumulation registers as printed (none of the library's kernels uses any)
+        acc = int(r["Accum_VGPR_Count"])
         lds = int(r["LDS_Block_Size"])
         wg = int(r["Workgroup_Size_X"]) * int(r["Workgroup_Size_Y"]) * int(r["Workgroup_Size_Z"])
         grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
