@@ -847,6 +847,21 @@ def main() -> int:
         mix = probe_res.get("adjoint_mix_gbs")
         gradient["adjoint_mix_ceiling_gbs"] = mix  # a plain streaming kernel with the same access mix
         gradient["adjoint_pass_frac_of_mix_ceiling"] = round(gradient["adjoint_pass_gbs"] / mix, 3) if mix else None
+        # the fused adjoint step's own access pattern (its 128 x 16 tiles and
+        # 32-plane chunks on this 256^3 grid) without arithmetic
+        adj_stream = None
+        try:
+            from paper_2204_03775_amd import probe
+
+            adj_stream = probe.measure_adjoint_stream(256, 256, 256, 32, 16)
+        except ImportError:
+            pass
+        gradient["adjoint_stream_measured"] = adj_stream
+        gradient["adjoint_pass_frac_of_adjoint_stream"] = (
+            round(gradient["adjoint_pass_gbs"] / adj_stream["alternating_gbs"], 3) if adj_stream else None)
+        if adj_stream:
+            log(f"adjoint step's access pattern alone: {adj_stream['alternating_gbs']:.0f} GB/s alternating; "
+                f"adjoint pass {gradient['adjoint_pass_frac_of_adjoint_stream']:.3f} of it")
         if not (gradient["finite"] and gradient["bitwise_equal_across_checkpointing"]
                 and gradient["bitwise_equal_fused_two_passes"]):
             log("error: gradient not finite or dependent on the checkpoint interval")

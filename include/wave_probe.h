@@ -75,6 +75,20 @@ int probe_step_stream(const float *a, float *b, const float *k, int nx, int ny, 
 int probe_step_stream16(const void *u, void *p, void *o, const void *k, int nx, int ny, int nz, int64_t pitch,
                         int64_t x0, int zc, int ty, int ry, int down, void *stream);
 
+/* The fused adjoint step's access pattern without its arithmetic, on FP32
+ * fields in the layout above (c, a, p, k) and an FP64 accumulator g with the
+ * same layout in 8-byte cells (16-byte aligned pointers): c and a read four
+ * planes ahead of the march (default policy), p and k at the plane
+ * (non-temporal), g read and written at the plane (default policy), and
+ * p = c ^ a ^ p ^ k written in place (non-temporal), 36 bytes per cell; the
+ * first 16 bytes of a thread's 32 accumulator bytes are XORed with c's 16,
+ * the second with a's.  Tiles of 32 x ty threads (ty 8 or 16), each thread
+ * 4 cells of one row, z-chunks of zc planes, as the adjoint kernel tiles a
+ * grid.  -1 for bad arguments (as probe_step_stream, and the accumulator's
+ * plane under 2 GiB). */
+int probe_adjoint_stream(const float *c, const float *a, float *p, const float *k, double *g, int nx, int ny,
+                         int nz, int64_t pitch, int64_t x0, int zc, int ty, int down, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -313,6 +313,63 @@ __global__ __launch_bounds__(32 * TY) void step_stream16_k(const void *u, void *
     }
 }
 
+// The fused adjoint step's access pattern without its arithmetic: FP32
+// fields c (phi^{m+1}) and a (the forward level) read four planes ahead of
+// the march with the default policy, p (phi^{m+2}) and k at the plane
+// non-temporally, the FP64 accumulator g (8-byte cells, same layout) read
+// and written at the plane with the default policy, and p overwritten in
+// place non-temporally: 36 bytes per cell.  Tiles of 32 x TY threads, each
+// thread 4 cells of one row (128 cells x TY rows), z-chunks of zc planes,
+// as the adjoint kernel tiles a grid.  p = c ^ a ^ p ^ k and the two
+// 16-byte halves of a thread's accumulator cells XORed with c and a.
+typedef unsigned u4raw __attribute__((vector_size(16)));
+
+template <int TY>
+__global__ __launch_bounds__(32 * TY) void adjoint_stream_k(const float *c, const float *a, float *p,
+                                                            const float *k, double *g, int nxq, int ny, int nz,
+                                                            long long pitch, long long plane_bytes, int x0, int zc,
+                                                            int ntx, int nty, int nwg, int down)
+{
+    const int per = gridDim.x >> 3;
+    const int lid = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (lid >= nwg)
+        return;
+    const int tx = lid % ntx, rest = lid / ntx, ty = rest % nty, ch = rest / nty;
+    const int z0 = ch * zc, z1 = min(z0 + zc, nz), len = z1 - z0;
+    const int q = tx * 32 + (int)(threadIdx.x % 32);
+    const int row = ty * TY + (int)(threadIdx.x / 32);
+    const bool in = q < nxq && row < ny;
+    const long long cell = (long long)(row + 4) * pitch + x0 + 4 * q;
+    const unsigned off = in ? 4u * unsigned(cell) : 0xffffffffu;    // FP32 fields
+    const unsigned goff = in ? 8u * unsigned(cell) : 0xffffffffu;   // accumulator
+    const long long gplane = 2 * plane_bytes;
+    const int dz = down ? -1 : 1;
+    const int zs = down ? z1 - 1 : z0;
+    auto grs = [&](int z) {
+        const char *b = reinterpret_cast<const char *>(g) + (long long)(z + 4) * gplane;
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(b), (short)0, (int)gplane, kRawWord3);
+    };
+    u4raw cn, an, pn, kn, g0, g1;
+    auto load = [&](int z) {
+        cn = __builtin_amdgcn_raw_buffer_load_b128(plane16(c, plane_bytes, z + 4 * dz), off, 0, kPolKeep);
+        an = __builtin_amdgcn_raw_buffer_load_b128(plane16(a, plane_bytes, z + 4 * dz), off, 0, kPolKeep);
+        pn = __builtin_amdgcn_raw_buffer_load_b128(plane16(p, plane_bytes, z), off, 0, kPolStream);
+        kn = __builtin_amdgcn_raw_buffer_load_b128(plane16(k, plane_bytes, z), off, 0, kPolStream);
+        g0 = __builtin_amdgcn_raw_buffer_load_b128(grs(z), goff, 0, kPolKeep);
+        g1 = __builtin_amdgcn_raw_buffer_load_b128(grs(z), goff + 16u, 0, kPolKeep);
+    };
+    load(zs);
+    for (int l = 0; l < len; ++l) {
+        const int z = zs + l * dz;
+        const u4raw vc = cn, va = an, vp = pn, vk = kn, w0 = g0, w1 = g1;
+        if (l + 1 < len)
+            load(z + dz);
+        __builtin_amdgcn_raw_buffer_store_b128(vc ^ va ^ vp ^ vk, plane16(p, plane_bytes, z), off, 0, kPolStream);
+        __builtin_amdgcn_raw_buffer_store_b128(w0 ^ vc, grs(z), goff, 0, kPolKeep);
+        __builtin_amdgcn_raw_buffer_store_b128(w1 ^ va, grs(z), goff + 16u, 0, kPolKeep);
+    }
+}
+
 bool bad(const void *p) { return !p || (reinterpret_cast<uintptr_t>(p) & 15u); }
 
 int grid_for(long long n4)
@@ -436,4 +493,30 @@ extern "C" int probe_step_stream16(const void *u, void *p, void *o, const void *
     STREAM16(32, 1)
 #undef STREAM16
     return -1;
+}
+
+extern "C" int probe_adjoint_stream(const float *c, const float *a, float *p, const float *k, double *g, int nx,
+                                    int ny, int nz, int64_t pitch, int64_t x0, int zc, int ty, int down,
+                                    void *stream)
+{
+    if (bad(c) || bad(a) || bad(p) || bad(k) || bad(g) || nx < 4 || (nx & 3) || ny < 1 || nz < 1 || zc < 1 ||
+        (pitch & 3) || (x0 & 3) || x0 < 4 || pitch < x0 + nx + 4 || (ty != 8 && ty != 16))
+        return -1;
+    const long long plane_bytes = (long long)pitch * (ny + 8) * 4;
+    if (2 * plane_bytes >= (1ll << 31))
+        return -1;
+    const int nxq = nx / 4;
+    const int ntx = (nxq + 31) / 32, nty = (ny + ty - 1) / ty, nch = (nz + zc - 1) / zc;
+    const long long nwg = (long long)ntx * nty * nch;
+    if (nwg > (1ll << 30))
+        return -1;
+    const int grid = int((nwg + 7) / 8 * 8);
+    if (ty == 8)
+        hipLaunchKernelGGL(adjoint_stream_k<8>, dim3(grid), dim3(256), 0, (hipStream_t)stream, c, a, p, k, g, nxq,
+                           ny, nz, (long long)pitch, plane_bytes, int(x0), zc, ntx, nty, int(nwg), down ? 1 : 0);
+    else
+        hipLaunchKernelGGL(adjoint_stream_k<16>, dim3(grid), dim3(512), 0, (hipStream_t)stream, c, a, p, k, g,
+                           nxq, ny, nz, (long long)pitch, plane_bytes, int(x0), zc, ntx, nty, int(nwg),
+                           down ? 1 : 0);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
 }

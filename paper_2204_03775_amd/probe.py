@@ -8,7 +8,8 @@ access mix) bandwidth in GB/s, for arrays of ``elements`` floats each
 launch, against that of a launch; ``measure_step_stream`` the bandwidth of
 the step's own access pattern (tiles, z-chunks, in-place write) without its
 arithmetic, with every launch marching up and with alternating directions,
-and ``measure_step_stream16`` the same for the 16-bit storage forms.
+``measure_step_stream16`` the same for the 16-bit storage forms and
+``measure_adjoint_stream`` for the fused adjoint step.
 """
 from __future__ import annotations
 
@@ -43,6 +44,8 @@ def _load():
     lib.probe_step_stream.restype = ci
     lib.probe_step_stream16.argtypes = [vp, vp, vp, vp, ci, ci, ci, i64, i64, ci, ci, ci, ci, vp]
     lib.probe_step_stream16.restype = ci
+    lib.probe_adjoint_stream.argtypes = [vp, vp, vp, vp, vp, ci, ci, ci, i64, i64, ci, ci, ci, vp]
+    lib.probe_adjoint_stream.restype = ci
     return lib
 
 
@@ -164,6 +167,63 @@ def measure_step_stream16(nx: int, ny: int, nz: int, zc: int, ty: int, ry: int, 
         out[f"{name}_gbs"] = round(bpp * nx * ny * nz / sec / 1e9, 1)
         out[f"{name}_us"] = round(sec * 1e6, 2)
     del f
+    return out
+
+
+def measure_adjoint_stream(nx: int, ny: int, nz: int, zc: int, ty: int = 16, launches: int = 20) -> dict:
+    """The fused adjoint step's access pattern without its arithmetic: GB/s
+    at 36 bytes per interior cell, launches swapping the two wave fields,
+    all marching up and alternating direction; tiles of 128 cells x ty rows
+    and z-chunks of zc planes, as the adjoint kernel tiles the grid."""
+    lib = _load()
+    x0 = 32
+    pitch = -(-(x0 + nx + 4) // 32) * 32
+    elems = pitch * (ny + 8) * (nz + 8)
+    f = [torch.randint(-2 ** 31, 2 ** 31 - 1, (elems,), dtype=torch.int32, device="cuda") for _ in range(4)]
+    g = torch.randint(-2 ** 31, 2 ** 31 - 1, (2 * elems,), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    s = stream.cuda_stream
+
+    def launch(c, p, down):
+        rc = lib.probe_adjoint_stream(c.data_ptr(), f[2].data_ptr(), p.data_ptr(), f[3].data_ptr(), g.data_ptr(),
+                                      nx, ny, nz, pitch, x0, zc, ty, int(down), s)
+        if rc != 0:
+            raise RuntimeError(f"probe_adjoint_stream failed (code {rc})")
+
+    # one launch checked against its definition over the whole fields
+    view = lambda t, w=1: t.view(nz + 8, ny + 8, w * pitch)
+    inner = lambda t, dz=0: view(t)[4 + dz:4 + dz + nz, 4:4 + ny, x0:x0 + nx]
+    c4, a4 = inner(f[0], 4), inner(f[2], 4)
+    want_p, want_g = f[1].clone(), g.clone()
+    inner(want_p).copy_(c4 ^ a4 ^ inner(f[1]) ^ inner(f[3]))
+    gi = view(want_g, 2)[4:4 + nz, 4:4 + ny, 2 * x0:2 * (x0 + nx)].reshape(nz, ny, nx // 4, 8)
+    gi[..., :4] ^= c4.reshape(nz, ny, nx // 4, 4)
+    gi[..., 4:] ^= a4.reshape(nz, ny, nx // 4, 4)
+    launch(f[0], f[1], False)
+    torch.cuda.synchronize()
+    ok = torch.equal(f[1], want_p) and torch.equal(g, want_g)
+    del want_p, want_g, gi, c4, a4
+    if not ok:
+        raise RuntimeError("adjoint-stream probe computed a wrong result")
+    out = {"bytes_per_point": 36, "nx": nx, "ny": ny, "nz": nz, "zchunk": zc, "tile": f"t128x{ty}_r1",
+           "launches": launches}
+    for name, alternate in (("ascending", False), ("alternating", True)):
+        def seq(count):
+            a, b = f[0], f[1]
+            for i in range(count):
+                launch(a, b, alternate and (i & 1))
+                a, b = b, a
+        seq(4)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        seq(launches)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / launches
+        out[f"{name}_gbs"] = round(36 * nx * ny * nz / sec / 1e9, 1)
+        out[f"{name}_us"] = round(sec * 1e6, 2)
+    del f, g
     return out
 
 
