@@ -3,7 +3,9 @@
 ``python -m paper_2204_03775_amd.probe [elements]`` prints one JSON line with
 the copy (1 read + 1 write) and read3-write1 (the propagator's per-update
 access mix) bandwidth in GB/s, for arrays of ``elements`` floats each
-(default: one 512^3 field in the propagator's padded layout).
+(default: one 512^3 field in the propagator's padded layout);
+``python -m paper_2204_03775_amd.probe step-stream NX NY NZ ZC`` the step's
+access pattern on that grid and z-chunk (``measure_step_stream``).
 ``measure_sync`` gives the cost of synchronising work-groups inside one
 launch, against that of a launch; ``measure_step_stream`` the bandwidth of
 the step's own access pattern (tiles, z-chunks, in-place write) without its
@@ -328,6 +330,11 @@ def measure(n: int, repeats: int = 20, with_adjoint_mix: bool = False) -> dict:
 
 
 if __name__ == "__main__":
+    if len(sys.argv) == 6 and sys.argv[1] == "step-stream":
+        # python -m paper_2204_03775_amd.probe step-stream NX NY NZ ZC
+        nx, ny, nz, zc = (int(v) for v in sys.argv[2:])
+        print(json.dumps(measure_step_stream(nx, ny, nz, zc, launches=6)), flush=True)
+        sys.exit(0)
     if len(sys.argv) > 1:
         n = int(sys.argv[1])
     else:
