@@ -525,6 +525,7 @@ def gradient_leg(reps: int):
     return {"workload": "256^3 x 800 steps FP32, 5 layers 1500-4500 m/s, +5% Gaussian anomaly "
                         "(sigma 8 cells, seed 2208), data from the model without it, 12 Hz "
                         "Ricker at (25,128,128), 128 receivers at z=22, 20-cell sponge",
+            "grid": [p.nx, p.ny, p.nz],
             "forward_ms": round(t_fwd * 1e3, 3),
             "gradient_ms": round(t_g50 * 1e3, 3), "checkpoint_every": info50[1],
             "checkpoint_gb": round(info50[3] / 1e9, 3),
@@ -847,13 +848,15 @@ def main() -> int:
         mix = probe_res.get("adjoint_mix_gbs")
         gradient["adjoint_mix_ceiling_gbs"] = mix  # a plain streaming kernel with the same access mix
         gradient["adjoint_pass_frac_of_mix_ceiling"] = round(gradient["adjoint_pass_gbs"] / mix, 3) if mix else None
-        # the fused adjoint step's own access pattern (its 128 x 16 tiles and
-        # 32-plane chunks on this 256^3 grid) without arithmetic
+        # the fused adjoint step's own access pattern without arithmetic, with
+        # the tiling the adjoint picks on this grid (128 x 16 tiles, 32-plane
+        # chunks: 256 work-groups)
         adj_stream = None
         try:
             from paper_2204_03775_amd import probe
 
-            adj_stream = probe.measure_adjoint_stream(256, 256, 256, 32, 16)
+            gx, gy, gz = gradient["grid"]
+            adj_stream = probe.measure_adjoint_stream(gx, gy, gz, 32, 16)
         except ImportError:
             pass
         gradient["adjoint_stream_measured"] = adj_stream
