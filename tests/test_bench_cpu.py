@@ -1,7 +1,8 @@
 """bench.py's command-line contract that needs no GPU: more than one GPU is
-refused with a message (the propagator runs on one GPU), and the paper's
+refused with a message (the propagator runs on one GPU), the paper's
 scaling-table figures it prints beside the MI355X rates are the tables'
-own values."""
+own values, and the 16-bit pattern probe is left out for tilings it does
+not mirror."""
 import os
 import subprocess
 import sys
@@ -32,3 +33,13 @@ def test_paper_scaling_figures():
     # Table 3: 100,000 steps
     for (nx, ny, nz), (thr, t_wse) in bench.PAPER_TABLE3.items():
         assert abs(nx * ny * nz * 100000 / t_wse / 1e9 - thr) / thr < 0.01
+
+
+def test_16bit_probe_is_skipped_for_tilings_it_does_not_cover():
+    # the probe mirrors 128-cell-wide tiles of 8, 16 or 32 thread rows; other
+    # tilings get no pattern ceiling (None) rather than a mismatched one
+    sys.path.insert(0, ROOT)
+    import bench
+
+    for name in ("t256x8_r1", "t64x16_r1", "t128x24_r1", "t128x32_r4", "naive", "auto"):
+        assert bench.step_stream16(None, name, 128, True) is None, name
